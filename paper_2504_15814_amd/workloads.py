@@ -1,0 +1,270 @@
+"""Seeded synthetic face batches for tests and benchmarks.
+
+This module holds no transfer arithmetic: it only places hanging faces in the
+unit cube, fills both face buffers with a smooth field sampled at the cell
+centres, and lays out the per-face descriptors.  The test oracle and the HIP
+library both consume what it produces; neither is imported here.
+
+Buffer convention (the library's header states the same contract): a face
+whose normal is axis a = o mod 3 stores 2k x p x p cells, axis 0 fastest and
+the unknowns of a cell innermost; normal index [0, k) is the - side; the fine
+patch is on the + side for o < 3.  Fine subface s = sb + 3 sc covers fine
+columns [sb p, (sb + 1) p) x [sc p, (sc + 1) p) of the coarse face.
+
+Workloads (all seeds are 15814 + workload number; draw order is fixed below):
+
+1  64 faces, p = 9, k = 3, U = 1; o = f mod 6, s = (f div 6) mod 9; a random
+   cubic plus sin(kappa . x), kappa_i ~ U[0.5, 2].
+2  20,000 faces, p = 9, k = 3, U = 59; o, s uniform; per unknown 8 Gaussian
+   bumps (amplitude N(0,1), centre U[0,1]^3, width U[0.2, 1]) plus
+   N(0, 1e-3^2) noise on every stored value.
+3  workload 2 with unknown u scaled by 10^(-6 + 9 u / 58).
+4  50,000 faces: p in {6, 9, 12} at 30/50/20 %, k in {2, 3}, scheme and
+   direction uniform, U = 59, fields as workload 2.
+Faces sit on a grid of 9^3 coarse patches (h_c = 1/81, h_f = 1/243).
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+SEED_BASE = 15814
+H_FINE = 1.0 / 243.0
+
+
+@dataclass
+class FaceBatch:
+    """Independent hanging faces sharing (p, k, U).  Every face owns one coarse
+    and one fine buffer of 2k p^2 U elements inside the flat `coarse` and
+    `fine` tensors, at the element offsets given per face."""
+
+    p: int
+    k: int
+    U: int
+    orientation: torch.Tensor  # int8 [n]
+    subface: torch.Tensor  # int8 [n]
+    coarse_offset: torch.Tensor  # int64 [n]
+    fine_offset: torch.Tensor  # int64 [n]
+    coarse: torch.Tensor  # float [n * 2k p^2 U]
+    fine: torch.Tensor  # float [n * 2k p^2 U]
+    origin: torch.Tensor = field(default=None)  # float64 [n, 3] physical corner
+
+    @property
+    def n(self):
+        return int(self.orientation.numel())
+
+    @property
+    def face_elems(self):
+        return 2 * self.k * self.p * self.p * self.U
+
+    def to(self, device):
+        kw = {}
+        for name in ("orientation", "subface", "coarse_offset", "fine_offset", "coarse", "fine", "origin"):
+            v = getattr(self, name)
+            kw[name] = None if v is None else v.to(device)
+        return FaceBatch(self.p, self.k, self.U, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Cell centres of a face buffer, in fine-mesh units relative to the face
+# (face plane at normal coordinate 0, coarse face lower corner at 0).
+# ---------------------------------------------------------------------------
+def _grid(o, p, k, device):
+    a = o % 3
+    ext = [p, p, p]
+    ext[a] = 2 * k
+    i2, i1, i0 = torch.meshgrid(
+        torch.arange(ext[2], device=device),
+        torch.arange(ext[1], device=device),
+        torch.arange(ext[0], device=device),
+        indexing="ij",
+    )
+    return a, torch.stack([i0.reshape(-1), i1.reshape(-1), i2.reshape(-1)], dim=1).to(torch.float64)
+
+
+def coarse_centres(o, p, k, device="cpu"):
+    a, idx = _grid(o, p, k, device)
+    pos = 3.0 * idx + 1.5
+    pos[:, a] = 3.0 * (idx[:, a] - k) + 1.5
+    return pos
+
+
+def fine_centres(o, p, k, s, device="cpu"):
+    a, idx = _grid(o, p, k, device)
+    b, c = [ax for ax in range(3) if ax != a]
+    pos = idx + 0.5
+    pos[:, a] = idx[:, a] - k + 0.5
+    pos[:, b] += (s % 3) * p
+    pos[:, c] += (s // 3) * p
+    return pos
+
+
+# ---------------------------------------------------------------------------
+# Smooth fields
+# ---------------------------------------------------------------------------
+@dataclass
+class BumpField:
+    """Sum of Gaussian bumps per unknown: amp [U, B], centre [U, B, 3],
+    width [U, B]; optional per-unknown scale [U]."""
+
+    amp: torch.Tensor
+    centre: torch.Tensor
+    width: torch.Tensor
+    scale: torch.Tensor = None
+
+    def __call__(self, x):
+        """x: [N, 3] physical positions -> [N, U] values (float64)."""
+        U, B = self.amp.shape
+        dev = x.device
+        out = torch.zeros(x.shape[0], U, dtype=torch.float64, device=dev)
+        amp, cen, wid = self.amp.to(dev), self.centre.to(dev), self.width.to(dev)
+        for j in range(B):
+            d2 = ((x[:, None, :] - cen[None, :, j, :]) ** 2).sum(-1)  # [N, U]
+            out += amp[None, :, j] * torch.exp(-d2 / (2.0 * wid[None, :, j] ** 2))
+        if self.scale is not None:
+            out *= self.scale.to(dev)[None, :]
+        return out
+
+
+@dataclass
+class CubicSineField:
+    """sum_{|alpha|<=3} a_alpha (x - 1/2)^alpha + sin(kappa . x), one unknown."""
+
+    coeffs: torch.Tensor  # [20]
+    kappa: torch.Tensor  # [3]
+
+    def __call__(self, x):
+        y = x - 0.5
+        out = torch.sin(x @ self.kappa.to(x.device))
+        i = 0
+        for t in range(4):
+            for e0 in range(t + 1):
+                for e1 in range(t + 1 - e0):
+                    e2 = t - e0 - e1
+                    out = out + self.coeffs[i].item() * y[:, 0] ** e0 * y[:, 1] ** e1 * y[:, 2] ** e2
+                    i += 1
+        return out[:, None]
+
+
+def bump_field(gen, U, n_bumps=8, scaled=False):
+    amp = torch.randn(U, n_bumps, generator=gen, dtype=torch.float64)
+    centre = torch.rand(U, n_bumps, 3, generator=gen, dtype=torch.float64)
+    width = 0.2 + 0.8 * torch.rand(U, n_bumps, generator=gen, dtype=torch.float64)
+    scale = None
+    if scaled:
+        u = torch.arange(U, dtype=torch.float64)
+        scale = 10.0 ** (-6.0 + 9.0 * u / max(U - 1, 1))
+    return BumpField(amp, centre, width, scale)
+
+
+def cubic_sine_field(gen):
+    coeffs = torch.randn(20, generator=gen, dtype=torch.float64)
+    kappa = 0.5 + 1.5 * torch.rand(3, generator=gen, dtype=torch.float64)
+    return CubicSineField(coeffs, kappa)
+
+
+# ---------------------------------------------------------------------------
+# Face placement and buffer filling
+# ---------------------------------------------------------------------------
+def face_origins(gen, orientation, p):
+    """Physical position of each coarse face's corner: the face plane sits on an
+    interior patch boundary of a 9^3 patch grid and the face covers one patch
+    side (p coarse cells of width 1/81 when p = 9)."""
+    n = orientation.numel()
+    cell = torch.randint(1, 8, (n, 3), generator=gen).to(torch.float64) / 9.0
+    return cell
+
+
+def fill_buffers(batch, field_fn, noise_sigma=0.0, gen=None, chunk=2048):
+    """Sample field_fn at every cell centre of every face (both buffers), add
+    iid N(0, noise_sigma^2) noise, and store into batch.coarse / batch.fine."""
+    p, k, U = batch.p, batch.k, batch.U
+    dev = batch.coarse.device
+    ncell = 2 * k * p * p
+    E = ncell * U
+    cc = {o: coarse_centres(o, p, k, dev) for o in range(6)}
+    fc = {(o, s): fine_centres(o, p, k, s, dev) for o in range(6) for s in range(9)}
+    orient = batch.orientation.cpu().tolist()
+    sub = batch.subface.cpu().tolist()
+    origin = batch.origin.to(dev)
+    cview = batch.coarse.view(-1)
+    fview = batch.fine.view(-1)
+    coff = batch.coarse_offset.cpu().tolist()
+    foff = batch.fine_offset.cpu().tolist()
+    contiguous = coff == [f * E for f in range(batch.n)] and foff == coff
+    noise_gen = None
+    if noise_sigma:
+        seed = int(torch.randint(0, 2**62, (1,), generator=gen).item())
+        noise_gen = torch.Generator(device=dev).manual_seed(seed)
+    for f0 in range(0, batch.n, chunk):
+        f1 = min(batch.n, f0 + chunk)
+        pos_c = torch.stack([cc[orient[f]] for f in range(f0, f1)]) * H_FINE + origin[f0:f1, None, :]
+        pos_f = torch.stack([fc[(orient[f], sub[f])] for f in range(f0, f1)]) * H_FINE + origin[f0:f1, None, :]
+        vc = field_fn(pos_c.reshape(-1, 3)).reshape(f1 - f0, E)
+        vf = field_fn(pos_f.reshape(-1, 3)).reshape(f1 - f0, E)
+        if noise_sigma:
+            vc += noise_sigma * torch.randn(vc.shape, generator=noise_gen, dtype=torch.float64, device=dev)
+            vf += noise_sigma * torch.randn(vf.shape, generator=noise_gen, dtype=torch.float64, device=dev)
+        if contiguous:
+            cview[f0 * E : f1 * E] = vc.reshape(-1).to(cview.dtype)
+            fview[f0 * E : f1 * E] = vf.reshape(-1).to(fview.dtype)
+        else:
+            for i, f in enumerate(range(f0, f1)):
+                cview[coff[f] : coff[f] + E] = vc[i].to(cview.dtype)
+                fview[foff[f] : foff[f] + E] = vf[i].to(fview.dtype)
+
+
+def _contiguous_batch(orientation, subface, p, k, U, dtype, device, origin):
+    n = orientation.numel()
+    elems = 2 * k * p * p * U
+    offs = torch.arange(n, dtype=torch.int64) * elems
+    return FaceBatch(
+        p, k, U,
+        orientation.to(torch.int8).to(device),
+        subface.to(torch.int8).to(device),
+        offs.to(device),
+        offs.clone().to(device),
+        torch.zeros(n * elems, dtype=dtype, device=device),
+        torch.zeros(n * elems, dtype=dtype, device=device),
+        origin,
+    )
+
+
+def workload1(device="cpu", dtype=torch.float64):
+    """64 faces, p = 9, k = 3, U = 1, every (orientation, subface) pair present."""
+    gen = torch.Generator().manual_seed(SEED_BASE + 1)
+    f = torch.arange(64)
+    orient, sub = f % 6, (f // 6) % 9
+    origin = face_origins(gen, orient, 9)
+    batch = _contiguous_batch(orient, sub, 9, 3, 1, dtype, device, origin)
+    fill_buffers(batch, cubic_sine_field(gen))
+    return batch
+
+
+def uniform_faces(n, p, k, U, seed, device="cpu", dtype=torch.float64, scaled=False, noise=1e-3):
+    """n faces with uniform orientation and subface, bump fields plus noise."""
+    gen = torch.Generator().manual_seed(seed)
+    orient = torch.randint(0, 6, (n,), generator=gen)
+    sub = torch.randint(0, 9, (n,), generator=gen)
+    origin = face_origins(gen, orient, p)
+    fieldfn = bump_field(gen, U, scaled=scaled)
+    batch = _contiguous_batch(orient, sub, p, k, U, dtype, device, origin)
+    fill_buffers(batch, fieldfn, noise_sigma=noise, gen=gen)
+    return batch
+
+
+def workload2(n_faces=20000, device="cpu", dtype=torch.float64, U=59):
+    """20,000 faces, p = 9, k = 3, U = 59 (CCZ4-sized state), bump fields."""
+    return uniform_faces(n_faces, 9, 3, U, SEED_BASE + 2, device, dtype)
+
+
+def workload3(n_faces=20000, device="cpu", dtype=torch.float64, U=59):
+    """Workload 2 with per-unknown magnitudes spanning 1e-6 .. 1e3."""
+    return uniform_faces(n_faces, 9, 3, U, SEED_BASE + 3, device, dtype, scaled=True)
+
+
+def sentinel_fill_(t, value=-7.25e11):
+    """Fill a destination buffer with a recognisable value."""
+    t.fill_(value)
+    return t
