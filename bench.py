@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the AMR face transfer on one MI355X.
+
+One step = the whole transfer on one batch: for each scheme (d-linear,
+Taylor-2, Taylor-3), restrict every hanging face into its coarse face and
+interpolate every fine halo from its coarse face.  Workload: 20,000
+independent hanging faces, patches of 9^3 cells, halo depth 3, 59 unknowns
+per cell (a CCZ4-sized state), float64, seeded synthetic smooth fields
+(Gaussian bumps plus 1e-3 noise).  Inputs are resident in HBM before timing.
+
+Reported value: ghost-cell-unknowns written per second (interpolated fine
+halo values plus restricted coarse values) over the timed steps.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "interpolated+restricted ghost-cell-unknowns/sec and % HBM peak; mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+SCHEME_NAMES = {1: "dlinear", 2: "taylor2", 3: "taylor3"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--faces", type=int, default=20000)
+    ap.add_argument("--cpu-faces", type=int, default=4000,
+                    help="faces in the oracle's CPU-baseline sample (0 disables it)")
+    ap.add_argument("--no-mixed", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(op, orientation, subface, U, elem_bytes):
+    """Per-face (distinct source cells with a nonzero weight + destination
+    cells) x U x element size, summed over the batch's (orientation, subface)
+    mix."""
+    import numpy as np
+
+    per = {}
+    for o in range(6):
+        for s in range(9):
+            rows, cols, vals = op.segment(o, s)
+            per[(o, s)] = (len(np.unique(cols[vals != 0])) + len(np.unique(rows))) * U * elem_bytes
+    counts = np.zeros((6, 9), dtype=np.int64)
+    np.add.at(counts, (orientation, subface), 1)
+    return int(sum(per[(o, s)] * counts[o, s] for o in range(6) for s in range(9)))
+
+
+def run_steps(launches, steps, warmup, torch):
+    """Time `steps` passes over `launches` (list of (name, fn)); per-launch
+    durations come from events recorded on the launch stream."""
+    for _ in range(warmup):
+        for _, fn in launches:
+            fn()
+    torch.cuda.synchronize()
+    events = {name: [] for name, _ in launches}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for name, fn in launches:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            events[name].append((a, b))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms = {name: sum(a.elapsed_time(b) for a, b in ev) / len(ev) for name, ev in events.items()}
+    return (t1 - t0) * 1e3 / steps, kern_ms
+
+
+def cpu_baseline(batch, n_faces, torch):
+    """The FP64 oracle on the host, on the first n_faces faces of the same
+    batch; operators are built before timing (the paper times repeated calls
+    without reallocation)."""
+    import numpy as np
+    import threadpoolctl
+
+    import oracle
+
+    U, p, k = batch.U, batch.p, batch.k
+    E = batch.face_elems
+    coarse = batch.coarse[: n_faces * E].cpu().numpy()
+    fine = batch.fine[: n_faces * E].cpu().numpy()
+    o = batch.orientation[:n_faces].cpu().numpy()
+    s = batch.subface[:n_faces].cpu().numpy()
+    co = batch.coarse_offset[:n_faces].cpu().numpy()
+    fo = batch.fine_offset[:n_faces].cpu().numpy()
+    for scheme in (1, 2, 3):
+        for oo in range(6):
+            for ss in range(9):
+                oracle.interpolation_operator(scheme, p, k, oo, ss)
+                oracle.restriction_operator(scheme, p, k, oo, ss)
+    threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
+    t0 = time.perf_counter()
+    for scheme in (1, 2, 3):
+        oracle.restrict_faces(scheme, p, k, o, s, co, fo, U, fine, coarse)
+        oracle.interpolate_faces(scheme, p, k, o, s, co, fo, U, coarse, fine)
+    dt = time.perf_counter() - t0
+    produced = 3 * n_faces * (9 * k * (p // 3) ** 2 + k * (p // 3) ** 2) * U
+    return {
+        "value": produced / dt,
+        "unit": "ghost-cell-unknowns/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"first {n_faces} of {batch.n} faces, all 3 schemes x restrict+interpolate, "
+                  f"{dt:.1f} s wall on the host",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported "
+                                   "(faces would shard across GPUs by fine-patch owner)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2504_15814_amd import api
+    from paper_2504_15814_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    batch = wl.workload2(n_faces=args.faces, device=dev)
+    U, p, k, n = batch.U, batch.p, batch.k, batch.n
+    orient_np = batch.orientation.cpu().numpy()
+    sub_np = batch.subface.cpu().numpy()
+
+    def make_launches(dtype):
+        coarse_in = batch.coarse.to(dtype)
+        fine_in = batch.fine.to(dtype)
+        coarse_out = coarse_in.clone()
+        fine_out = fine_in.clone()
+        launches, ops = [], {}
+        for scheme in (1, 2, 3):
+            rop = api.build_transfer_operator(api.FT_RESTRICT, scheme, p, k)
+            iop = api.build_transfer_operator(api.FT_INTERPOLATE, scheme, p, k)
+            ops[("restrict", scheme)] = rop
+            ops[("interpolate", scheme)] = iop
+
+            def r(rop=rop):
+                api.restrict_faces(rop, batch.orientation, batch.subface, batch.coarse_offset,
+                                   batch.fine_offset, U, fine_in, coarse_out)
+
+            def i(iop=iop):
+                api.interpolate_faces(iop, batch.orientation, batch.subface, batch.coarse_offset,
+                                      batch.fine_offset, U, coarse_in, fine_out)
+
+            launches.append((f"restrict_{SCHEME_NAMES[scheme]}", r))
+            launches.append((f"interpolate_{SCHEME_NAMES[scheme]}", i))
+        return launches, ops, (coarse_out, fine_out)
+
+    launches, ops, _ = make_launches(torch.float64)
+    ms, kern_ms = run_steps(launches, args.steps, args.warmup, torch)
+    produced = 3 * n * (9 * k * (p // 3) ** 2 + k * (p // 3) ** 2) * U
+    value = produced / (ms * 1e-3)
+
+    kernels = {}
+    for (direction, scheme), op in ops.items():
+        name = f"{direction}_{SCHEME_NAMES[scheme]}"
+        nbytes = algorithmic_bytes(op, orient_np, sub_np, U, 8)
+        t = kern_ms[name]
+        kernels[name] = {"ms": round(t, 4), "alg_bytes": nbytes, "GB/s": round(nbytes / (t * 1e-3) / 1e9, 1)}
+    dom = max(kernels, key=lambda kk: kernels[kk]["ms"])
+    ach = kernels[dom]["GB/s"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    total_bytes = sum(v["alg_bytes"] for v in kernels.values())
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ghost-cell-unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "hanging faces p=9 k=3 U=59 FP64; dlinear+taylor2+taylor3; restrict+interpolate",
+                   "faces": n, "p": p, "k": k, "unknowns": U},
+        "hbm_frac_step": round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+
+    if not args.no_mixed:
+        del launches
+        mlaunches, mops, _ = make_launches(torch.float32)
+        mms, mkern = run_steps(mlaunches, args.steps, args.warmup, torch)
+        result["mixed_f32"] = {
+            "value": produced / (mms * 1e-3),
+            "ms_per_step": mms,
+            "speedup_vs_f64": ms / mms,
+            "kernels_ms": {kk: round(v, 4) for kk, v in mkern.items()},
+        }
+        del mlaunches, mops
+
+    if args.cpu_faces > 0:
+        result["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_faces, n), torch)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

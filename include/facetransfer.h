@@ -1,0 +1,197 @@
+/*
+ * facetransfer: transfer of halo data across 3:1 resolution transitions of a
+ * block-structured 3D Cartesian spacetree mesh, on AMD Instinct MI355X
+ * (gfx950).  Implements the interpolation and restriction of Stokes,
+ * Weinzierl, Zhang and Li, "Fast Higher-Order Interpolation and Restriction
+ * in ExaHyPE Avoiding Non-physical Reflections" (arXiv 2504.15814):
+ * the d-linear tensor-product baseline and the second- and third-order
+ * Taylor schemes, applied as one operator per face.
+ *
+ * ---------------------------------------------------------------------------
+ * Data layout (the paper stores face data "AoS lexicographically", Section
+ * 4.1; everything else below is this library's convention)
+ * ---------------------------------------------------------------------------
+ * A face buffer belongs to one face of a patch of p^3 cells with halo depth k
+ * (Section 2).  Orientation o in 0..5 names the normal axis a = o mod 3; the
+ * tangential axes b < c are the other two, in increasing order.  The buffer
+ * holds 2k cells along a and p along b and c; cell (i0, i1, i2) (indices
+ * along physical axes 0, 1, 2) has cell number (i2*e1 + i1)*e0 + i0 where
+ * e_a = 2k and e_b = e_c = p, and unknown u of that cell is element
+ * cell*U + u.  Normal index [0, k) is the - side of the face, [k, 2k) the +
+ * side.  For o < 3 the fine patch lies on the + side, for o >= 3 on the -
+ * side.
+ *
+ * A hanging (fine) face is one of the 3x3 subfaces of its coarse face
+ * (three-partitioning, Section 2); subface s = sb + 3*sc with sb, sc in 0..2
+ * covers coarse columns [sb*p/3, (sb+1)*p/3) x [sc*p/3, (sc+1)*p/3) of the
+ * coarse face.  Coarse and fine face buffers have the same shape.
+ *
+ * Interpolation (Q^f = P Q^c, Section 2) reads both halves of the coarse
+ * face buffer and writes the fine face buffer's coarse-side half (its halo).
+ * Restriction (Q^c = R Q^f, Section 2) reads the fine face buffer (both
+ * halves) and writes the part of the coarse face buffer's fine-side half that
+ * lies under the subface.  Both apply only the 1/9 segment of P or R that
+ * belongs to the subface, the same operator for every unknown.
+ *
+ * Schemes (Section 3, Appendix C): FT_DLINEAR is the tensor-product baseline
+ * (1D linear interpolation per axis with linear extrapolation at the face
+ * edges; restriction by averaging).  FT_TAYLOR2 / FT_TAYLOR3 evaluate, at
+ * every target centre, a Taylor polynomial of degree 2 / 3 about the nearest
+ * source cell, fitted by least squares with the constant pinned to that
+ * cell's value over a 3x3x3 box stencil (plus the two-away axial points for
+ * degree 3), shifted toward the face interior at face edges.  Coinciding
+ * centres are copied bit for bit.
+ *
+ * Supported sizes: p a multiple of 3 with 6 <= p <= 48; k in {2, 3};
+ * 1 <= U <= 4096.
+ *
+ * ---------------------------------------------------------------------------
+ * Ownership, streams and errors
+ * ---------------------------------------------------------------------------
+ * Every data pointer passed to an apply call is DEVICE memory owned by the
+ * caller.  Operators are owned by the library until destroyed; they are
+ * immutable after build and may be shared across threads and streams.
+ * Apply calls are asynchronous on the given HIP stream (NULL = the null
+ * stream), allocate nothing and never synchronise, so they may be captured
+ * into a HIP graph.
+ *
+ * All entry points return FT_OK or an error code and never throw; a message
+ * for the last failure on the calling thread is available from
+ * transfer_last_error().  Argument checks happen on the host before anything
+ * is launched.  Per-face descriptors live in device memory and are checked
+ * by the kernels: a face whose orientation, subface or offsets are out of
+ * range (offset < 0 or offset + 2k*p*p*U > the buffer's element count) is
+ * skipped, writes nothing, and is counted in the operator's device error
+ * counter (transfer_operator_errors).
+ *
+ * Aliasing: source and destination buffers must not overlap, except that
+ * several restriction faces may write disjoint segments of the same coarse
+ * face, and several interpolation faces may read the same coarse face.
+ */
+#ifndef FACETRANSFER_H
+#define FACETRANSFER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define FT_OK 0
+#define FT_ERR_INVALID 1     /* bad argument (null pointer, range, mismatch) */
+#define FT_ERR_UNSUPPORTED 2 /* valid but unsupported (p, k, scheme, dtype)  */
+#define FT_ERR_HIP 3         /* HIP runtime failure                           */
+#define FT_ERR_NOMEM 4       /* device or host allocation failed              */
+
+/* Directions. */
+#define FT_INTERPOLATE 0
+#define FT_RESTRICT 1
+
+/* Schemes. */
+#define FT_DLINEAR 1
+#define FT_TAYLOR2 2
+#define FT_TAYLOR3 3
+
+/* Element types of face buffers.
+ * FT_F64: float64 storage, float64 arithmetic.
+ * FT_F32: float32 storage; interpolation sums in float32 with float32
+ *         weights, restriction sums in float64 (extrapolation weights have
+ *         a large 1-norm, so cancellation decides the accuracy there). */
+#define FT_F64 0
+#define FT_F32 1
+
+/* Build flags. */
+#define FT_BUILD_HOST_ONLY 1 /* build the weight tables on the host only; the
+                                operator can be inspected but not applied  */
+
+typedef struct ft_operator ft_operator;
+
+/* Build the transfer operator for one (direction, scheme, p, k).
+ * The Taylor fits and d-linear weights are assembled in extended precision on
+ * the host and rounded to float64 (and float32) weight tables, one dense block
+ * per class of expansion cell (Section 3: the matrices are precomputed once
+ * instead of per call), then copied to the current HIP device unless
+ * FT_BUILD_HOST_ONLY is set.
+ * out: receives the handle (library-owned; release with
+ *      destroy_transfer_operator).
+ * Errors: FT_ERR_INVALID (null out, unknown direction / scheme),
+ *         FT_ERR_UNSUPPORTED (p, k outside the supported set),
+ *         FT_ERR_NOMEM, FT_ERR_HIP. */
+int build_transfer_operator(int direction, int scheme, int p, int k, int flags,
+                            ft_operator** out);
+
+/* Release an operator; NULL is accepted and ignored.  The caller must make
+ * sure no launch that uses it is still pending. */
+int destroy_transfer_operator(ft_operator* op);
+
+/* Interpolate fine halo layers from coarse face data (Section 2, Q^f = P Q^c;
+ * Section 3, Taylor expansion about the containing coarse cell).
+ * op            : an FT_INTERPOLATE operator built for the device in use.
+ * n_faces       : number of hanging faces (0 is a no-op).
+ * orientation   : device int8[n_faces], 0..5.
+ * subface       : device int8[n_faces], 0..8.
+ * coarse_offset : device int64[n_faces], element offset of each face's coarse
+ *                 face buffer inside `coarse`.
+ * fine_offset   : device int64[n_faces], element offset of each fine face
+ *                 buffer inside `fine`.
+ * unknowns      : U, unknowns per cell (AoS, innermost).
+ * dtype         : FT_F64 or FT_F32, element type of both buffers.
+ * coarse        : device, coarse_elems elements, read only.
+ * fine          : device, fine_elems elements; only the halo (coarse-side)
+ *                 half of each referenced fine face buffer is written.
+ * stream        : hipStream_t (NULL for the null stream).
+ * Errors (host-side, nothing launched): FT_ERR_INVALID, FT_ERR_UNSUPPORTED;
+ * FT_ERR_HIP if the launch fails. */
+int interpolate_faces(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                      const int8_t* subface, const int64_t* coarse_offset,
+                      const int64_t* fine_offset, int unknowns, int dtype,
+                      const void* coarse, int64_t coarse_elems, void* fine,
+                      int64_t fine_elems, void* stream);
+
+/* Restrict fine face data into the coarse face's fine-side half (Section 2,
+ * Q^c = R Q^f; Section 3, Taylor expansion about the fine cell nearest each
+ * coarse centre: injection where they coincide, extrapolation elsewhere).
+ * Arguments as for interpolate_faces, with `fine` read only and `coarse`
+ * written: per face, the (p/3)^2 * k cells of the coarse face's fine-side half
+ * that lie under the subface. */
+int restrict_faces(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                   const int8_t* subface, const int64_t* coarse_offset,
+                   const int64_t* fine_offset, int unknowns, int dtype, const void* fine,
+                   int64_t fine_elems, void* coarse, int64_t coarse_elems, void* stream);
+
+/* Operator facts, written to info[0..n_info) (host memory):
+ * [0] direction  [1] scheme  [2] p  [3] k
+ * [4] rows per expansion cell (interpolation 9k, restriction k)
+ * [5] expansion cells per subface ((p/3)^2)
+ * [6] number of distinct weight blocks  [7] largest block width (stencil)
+ * [8] nonzero weights in one subface segment (orientation 0, subface 4)
+ * [9] bytes of the float64 weight tables
+ * Errors: FT_ERR_INVALID for a null op / info or n_info < 1. */
+int transfer_operator_info(const ft_operator* op, int64_t* info, int n_info);
+
+/* Export the 1/9 segment of the operator for one (orientation, subface) in
+ * physical cell numbering, as COO triplets into caller-owned host arrays of
+ * `capacity` entries: rows[] are destination cell numbers, cols[] source cell
+ * numbers, vals[] float64 weights.  *n_entries receives the count (also when
+ * capacity is too small, in which case nothing is written and
+ * FT_ERR_INVALID is returned).  Host only; needs no device. */
+int transfer_operator_segment(const ft_operator* op, int orientation, int subface,
+                              int64_t capacity, int64_t* rows, int64_t* cols, double* vals,
+                              int64_t* n_entries);
+
+/* Read (and optionally reset) the operator's device count of skipped faces.
+ * Synchronises the device; not for use inside graph capture. */
+int transfer_operator_errors(const ft_operator* op, int64_t* n_skipped, int reset);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* transfer_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int transfer_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FACETRANSFER_H */

@@ -1,0 +1,152 @@
+"""Python binding of the C ABI in include/facetransfer.h, same names.
+
+Tensors are torch tensors on the GPU; the binding passes their data pointers
+and element counts, the current HIP stream, and raises FTError on any
+non-zero return code.  Every step of the transfer runs in the HIP library.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+FT_OK, FT_ERR_INVALID, FT_ERR_UNSUPPORTED, FT_ERR_HIP, FT_ERR_NOMEM = 0, 1, 2, 3, 4
+FT_INTERPOLATE, FT_RESTRICT = 0, 1
+FT_DLINEAR, FT_TAYLOR2, FT_TAYLOR3 = 1, 2, 3
+FT_F64, FT_F32 = 0, 1
+FT_BUILD_HOST_ONLY = 1
+
+_DTYPES = {torch.float64: FT_F64, torch.float32: FT_F32}
+
+
+class FTError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.load().transfer_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with code {code}: {msg}")
+        self.code = code
+
+
+def _check(code, where):
+    if code != FT_OK:
+        raise FTError(code, where)
+
+
+class TransferOperator:
+    """Owns an ft_operator handle."""
+
+    def __init__(self, handle, direction, scheme, p, k):
+        self._h = handle
+        self.direction, self.scheme, self.p, self.k = direction, scheme, p, k
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("operator already destroyed")
+        return self._h
+
+    def info(self):
+        buf = (ctypes.c_int64 * 10)()
+        _check(_lib.load().transfer_operator_info(self.handle, buf, 10), "transfer_operator_info")
+        keys = ("direction", "scheme", "p", "k", "rows_per_anchor", "anchors", "blocks",
+                "max_width", "nnz_segment", "weight_bytes")
+        return dict(zip(keys, list(buf)))
+
+    def segment(self, orientation, subface):
+        """COO (rows, cols, vals) of the physical 1/9 segment."""
+        lib = _lib.load()
+        n = ctypes.c_int64(0)
+        lib.transfer_operator_segment(self.handle, orientation, subface, 0, None, None, None, ctypes.byref(n))
+        rows = np.zeros(n.value, dtype=np.int64)
+        cols = np.zeros(n.value, dtype=np.int64)
+        vals = np.zeros(n.value, dtype=np.float64)
+        _check(
+            lib.transfer_operator_segment(
+                self.handle, orientation, subface, n.value,
+                rows.ctypes.data_as(_lib.c_int64_p), cols.ctypes.data_as(_lib.c_int64_p),
+                vals.ctypes.data_as(_lib.c_double_p), ctypes.byref(n)),
+            "transfer_operator_segment",
+        )
+        return rows, cols, vals
+
+    def errors(self, reset=True):
+        n = ctypes.c_int64(0)
+        _check(_lib.load().transfer_operator_errors(self.handle, ctypes.byref(n), int(reset)),
+               "transfer_operator_errors")
+        return n.value
+
+    def destroy(self):
+        if self._h:
+            _lib.load().destroy_transfer_operator(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def build_transfer_operator(direction, scheme, p, k, flags=0):
+    h = ctypes.c_void_p()
+    _check(_lib.load().build_transfer_operator(direction, scheme, p, k, flags, ctypes.byref(h)),
+           "build_transfer_operator")
+    return TransferOperator(h.value, direction, scheme, p, k)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _descriptors(orientation, subface, coarse_offset, fine_offset):
+    for name, t, dt in (("orientation", orientation, torch.int8), ("subface", subface, torch.int8),
+                        ("coarse_offset", coarse_offset, torch.int64), ("fine_offset", fine_offset, torch.int64)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {dt} tensor")
+    n = orientation.numel()
+    if not (subface.numel() == coarse_offset.numel() == fine_offset.numel() == n):
+        raise ValueError("descriptor arrays differ in length")
+    return n
+
+
+def interpolate_faces(op, orientation, subface, coarse_offset, fine_offset, unknowns, coarse, fine, stream=None):
+    """Fill the halo half of every fine face buffer from its coarse face."""
+    n = _descriptors(orientation, subface, coarse_offset, fine_offset)
+    if coarse.dtype != fine.dtype or coarse.dtype not in _DTYPES:
+        raise TypeError("coarse and fine must share dtype float64 or float32")
+    _check(
+        _lib.load().interpolate_faces(
+            op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
+            unknowns, _DTYPES[coarse.dtype], _ptr(coarse), coarse.numel(), _ptr(fine), fine.numel(),
+            _stream_ptr(stream)),
+        "interpolate_faces",
+    )
+
+
+def restrict_faces(op, orientation, subface, coarse_offset, fine_offset, unknowns, fine, coarse, stream=None):
+    """Fill each fine face's segment of its coarse face's fine-side half."""
+    n = _descriptors(orientation, subface, coarse_offset, fine_offset)
+    if coarse.dtype != fine.dtype or coarse.dtype not in _DTYPES:
+        raise TypeError("coarse and fine must share dtype float64 or float32")
+    _check(
+        _lib.load().restrict_faces(
+            op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
+            unknowns, _DTYPES[fine.dtype], _ptr(fine), fine.numel(), _ptr(coarse), coarse.numel(),
+            _stream_ptr(stream)),
+        "restrict_faces",
+    )
+
+
+def transfer_last_error():
+    return _lib.load().transfer_last_error().decode(errors="replace")
+
+
+def transfer_version():
+    return _lib.load().transfer_version()

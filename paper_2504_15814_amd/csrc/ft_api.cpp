@@ -1,0 +1,303 @@
+// C ABI of the face-transfer library: argument checking, operator lifetime,
+// device upload and error reporting.  No exception crosses this boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "facetransfer.h"
+#include "ft_internal.h"
+#include "ft_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return FT_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void free_device(ft_operator* op) {
+  if (!op->on_device) return;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(op->device);
+  if (op->d_stencil) (void)hipFree(op->d_stencil);
+  if (op->d_w64) (void)hipFree(op->d_w64);
+  if (op->d_w32) (void)hipFree(op->d_w32);
+  if (op->d_errors) (void)hipFree(op->d_errors);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  op->d_stencil = nullptr;
+  op->d_w64 = nullptr;
+  op->d_w32 = nullptr;
+  op->d_errors = nullptr;
+  op->on_device = false;
+}
+
+int upload(ft_operator* op) {
+  std::vector<int> pts;
+  std::vector<double> w64;
+  std::vector<float> w32;
+  ft::DevOp& d = op->dev;
+  d.direction = op->direction;
+  d.scheme = op->scheme;
+  d.p = op->p;
+  d.k = op->k;
+  d.R = op->R;
+  d.E = op->E;
+  d.copy_row = op->copy_row;
+  d.copy_n = op->copy_n;
+  for (int c = 0; c < ft::kClasses; ++c) {
+    const ft::HostBlock& b = op->blocks[c];
+    d.width[c] = b.width;
+    d.start[c] = (int)pts.size();
+    pts.insert(pts.end(), b.points.begin(), b.points.end());
+    w64.insert(w64.end(), b.weights.begin(), b.weights.end());
+  }
+  w32.resize(w64.size());
+  for (size_t i = 0; i < w64.size(); ++i) w32[i] = (float)w64[i];
+  if (pts.empty()) return fail(FT_ERR_INVALID, "operator has no weights");
+  hipError_t e = hipGetDevice(&op->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  op->on_device = true;  // so that free_device releases partial allocations
+  if ((e = hipMalloc(&op->d_stencil, pts.size() * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&op->d_w64, w64.size() * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&op->d_w32, w32.size() * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&op->d_errors, sizeof(int))) != hipSuccess) {
+    free_device(op);
+    return e == hipErrorOutOfMemory ? fail(FT_ERR_NOMEM, "device allocation failed")
+                                    : hip_fail(e, "hipMalloc");
+  }
+  if ((e = hipMemcpy(op->d_stencil, pts.data(), pts.size() * sizeof(int), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(op->d_w64, w64.data(), w64.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(op->d_w32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemset(op->d_errors, 0, sizeof(int))) != hipSuccess) {
+    free_device(op);
+    return hip_fail(e, "uploading operator tables");
+  }
+  d.stencil = op->d_stencil;
+  d.w64 = op->d_w64;
+  d.w32 = op->d_w32;
+  return FT_OK;
+}
+
+int check_apply(const ft_operator* op, int direction, int64_t n_faces, const void* orientation,
+                const void* subface, const void* so, const void* dof, int unknowns, int dtype,
+                const void* src, int64_t src_elems, const void* dst, int64_t dst_elems) {
+  if (!op) return fail(FT_ERR_INVALID, "operator is NULL");
+  if (op->direction != direction)
+    return fail(FT_ERR_INVALID, direction == FT_INTERPOLATE
+                                    ? "operator was built for restriction"
+                                    : "operator was built for interpolation");
+  if (!op->on_device) return fail(FT_ERR_INVALID, "operator was built host-only");
+  if (n_faces < 0) return fail(FT_ERR_INVALID, "n_faces < 0");
+  if (unknowns < 1 || unknowns > 4096) return fail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
+  if (dtype != FT_F64 && dtype != FT_F32) return fail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (src_elems < 0 || dst_elems < 0) return fail(FT_ERR_INVALID, "negative buffer size");
+  if (n_faces == 0) return FT_OK;
+  if (!orientation || !subface || !so || !dof || !src || !dst)
+    return fail(FT_ERR_INVALID, "NULL descriptor or buffer pointer");
+  if (src == dst) return fail(FT_ERR_INVALID, "source and destination alias");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != op->device) return fail(FT_ERR_INVALID, "operator belongs to another device");
+  return FT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int build_transfer_operator(int direction, int scheme, int p, int k, int flags,
+                            ft_operator** out) {
+  if (!out) return fail(FT_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (direction != FT_INTERPOLATE && direction != FT_RESTRICT)
+    return fail(FT_ERR_INVALID, "direction must be FT_INTERPOLATE or FT_RESTRICT");
+  if (scheme != FT_DLINEAR && scheme != FT_TAYLOR2 && scheme != FT_TAYLOR3)
+    return fail(FT_ERR_INVALID, "scheme must be FT_DLINEAR, FT_TAYLOR2 or FT_TAYLOR3");
+  if (p < 6 || p > ft::kMaxP || p % 3 != 0)
+    return fail(FT_ERR_UNSUPPORTED, "p must be a multiple of 3 in [6, 48]");
+  if (k != 2 && k != 3) return fail(FT_ERR_UNSUPPORTED, "k must be 2 or 3");
+  if (flags & ~FT_BUILD_HOST_ONLY) return fail(FT_ERR_INVALID, "unknown flags");
+  ft_operator* op = new (std::nothrow) ft_operator();
+  if (!op) return fail(FT_ERR_NOMEM, "host allocation failed");
+  op->direction = direction;
+  op->scheme = scheme;
+  op->p = p;
+  op->k = k;
+  std::string err;
+  try {
+    err = ft::build_tables(op);
+  } catch (const std::bad_alloc&) {
+    delete op;
+    return fail(FT_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    delete op;
+    return fail(FT_ERR_INVALID, "operator build failed");
+  }
+  if (!err.empty()) {
+    delete op;
+    return fail(FT_ERR_UNSUPPORTED, err);
+  }
+  if (!(flags & FT_BUILD_HOST_ONLY)) {
+    const int rc = upload(op);
+    if (rc != FT_OK) {
+      delete op;
+      return rc;
+    }
+  }
+  *out = op;
+  return ok();
+}
+
+int destroy_transfer_operator(ft_operator* op) {
+  if (!op) return ok();
+  free_device(op);
+  delete op;
+  return ok();
+}
+
+int interpolate_faces(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                      const int8_t* subface, const int64_t* coarse_offset,
+                      const int64_t* fine_offset, int unknowns, int dtype, const void* coarse,
+                      int64_t coarse_elems, void* fine, int64_t fine_elems, void* stream) {
+  int rc = check_apply(op, FT_INTERPOLATE, n_faces, orientation, subface, coarse_offset,
+                       fine_offset, unknowns, dtype, coarse, coarse_elems, fine, fine_elems);
+  if (rc != FT_OK || n_faces == 0) return rc == FT_OK ? ok() : rc;
+  ft::LaunchArgs la{n_faces, orientation, subface, coarse_offset, fine_offset, unknowns, dtype,
+                    coarse, coarse_elems, fine, fine_elems, op->d_errors};
+  hipError_t e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "interpolate_faces launch");
+  return ok();
+}
+
+int restrict_faces(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                   const int8_t* subface, const int64_t* coarse_offset,
+                   const int64_t* fine_offset, int unknowns, int dtype, const void* fine,
+                   int64_t fine_elems, void* coarse, int64_t coarse_elems, void* stream) {
+  int rc = check_apply(op, FT_RESTRICT, n_faces, orientation, subface, fine_offset,
+                       coarse_offset, unknowns, dtype, fine, fine_elems, coarse, coarse_elems);
+  if (rc != FT_OK || n_faces == 0) return rc == FT_OK ? ok() : rc;
+  ft::LaunchArgs la{n_faces, orientation, subface, fine_offset, coarse_offset, unknowns, dtype,
+                    fine, fine_elems, coarse, coarse_elems, op->d_errors};
+  hipError_t e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "restrict_faces launch");
+  return ok();
+}
+
+int transfer_operator_info(const ft_operator* op, int64_t* info, int n_info) {
+  if (!op || !info || n_info < 1) return fail(FT_ERR_INVALID, "NULL op / info or n_info < 1");
+  int64_t blocks = 0, widest = 0, wbytes = 0;
+  for (int c = 0; c < ft::kClasses; ++c) {
+    if (op->blocks[c].width == 0) continue;
+    ++blocks;
+    widest = std::max<int64_t>(widest, op->blocks[c].width);
+    wbytes += (int64_t)op->blocks[c].weights.size() * 8;
+  }
+  int64_t nnz = 0;
+  {
+    // Nonzero weights of the (orientation 0, subface 4) segment.
+    const int E = op->E;
+    for (int ec = 0; ec < E; ++ec)
+      for (int eb = 0; eb < E; ++eb) {
+        const int ab = op->direction == 0 ? E + eb : 3 * eb + 1;
+        const int ac = op->direction == 0 ? E + ec : 3 * ec + 1;
+        const auto& blk = op->blocks[ft::axis_class(ab, op->p) * ft::kAxisClasses +
+                                     ft::axis_class(ac, op->p)];
+        for (double w : blk.weights) nnz += (w != 0.0);
+      }
+  }
+  const int64_t vals[10] = {op->direction, op->scheme, op->p, op->k, op->R,
+                            (int64_t)op->E * op->E, blocks, widest, nnz, wbytes};
+  for (int i = 0; i < n_info && i < 10; ++i) info[i] = vals[i];
+  for (int i = 10; i < n_info; ++i) info[i] = 0;
+  return ok();
+}
+
+int transfer_operator_segment(const ft_operator* op, int orientation, int subface,
+                              int64_t capacity, int64_t* rows, int64_t* cols, double* vals,
+                              int64_t* n_entries) {
+  if (!op || !n_entries) return fail(FT_ERR_INVALID, "NULL op or n_entries");
+  if (orientation < 0 || orientation > 5 || subface < 0 || subface > 8)
+    return fail(FT_ERR_INVALID, "orientation must be 0..5 and subface 0..8");
+  const int p = op->p, k = op->k, E = op->E, R = op->R;
+  const ft::FaceStrides st = ft::face_strides(orientation % 3, p, k);
+  int nbase, nsign;
+  ft::normal_map(op->direction, orientation, k, &nbase, &nsign);
+  const int sb = subface % 3, sc = subface / 3;
+  std::vector<int64_t> rr, cc;
+  std::vector<double> vv;
+  for (int ec = 0; ec < E; ++ec)
+    for (int eb = 0; eb < E; ++eb) {
+      const int ab = op->direction == 0 ? sb * E + eb : 3 * eb + 1;
+      const int ac = op->direction == 0 ? sc * E + ec : 3 * ec + 1;
+      const auto& blk =
+          op->blocks[ft::axis_class(ab, p) * ft::kAxisClasses + ft::axis_class(ac, p)];
+      const int anchor = ab * st.sb + ac * st.sc;
+      for (int r = 0; r < R; ++r) {
+        int dcell;
+        if (op->direction == 0) {
+          const int g = r / 9, tb = (r / 3) % 3, tc = r % 3;
+          dcell = (nbase + nsign * g) * st.sa + (3 * eb + tb) * st.sb + (3 * ec + tc) * st.sc;
+        } else {
+          dcell = (nbase + nsign * r) * st.sa + (sb * E + eb) * st.sb + (sc * E + ec) * st.sc;
+        }
+        for (int q = 0; q < blk.width; ++q) {
+          const double w = blk.weights[(size_t)q * R + r];
+          if (w == 0.0) continue;
+          int n, db, dc;
+          ft::unpack_point(blk.points[q], &n, &db, &dc);
+          rr.push_back(dcell);
+          cc.push_back(anchor + (nbase + nsign * n) * st.sa + db * st.sb + dc * st.sc);
+          vv.push_back(w);
+        }
+      }
+    }
+  *n_entries = (int64_t)rr.size();
+  if (capacity < (int64_t)rr.size()) return fail(FT_ERR_INVALID, "capacity too small");
+  if (!rows || !cols || !vals) return fail(FT_ERR_INVALID, "NULL output array");
+  std::memcpy(rows, rr.data(), rr.size() * sizeof(int64_t));
+  std::memcpy(cols, cc.data(), cc.size() * sizeof(int64_t));
+  std::memcpy(vals, vv.data(), vv.size() * sizeof(double));
+  return ok();
+}
+
+int transfer_operator_errors(const ft_operator* op, int64_t* n_skipped, int reset) {
+  if (!op || !n_skipped) return fail(FT_ERR_INVALID, "NULL op or n_skipped");
+  if (!op->on_device) return fail(FT_ERR_INVALID, "operator was built host-only");
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  hipError_t e = hipSetDevice(op->device);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  int h = 0;
+  if (e == hipSuccess) e = hipMemcpy(&h, op->d_errors, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset) e = hipMemset(op->d_errors, 0, sizeof(int));
+  if (prev >= 0) (void)hipSetDevice(prev);
+  if (e != hipSuccess) return hip_fail(e, "reading the error counter");
+  *n_skipped = h;
+  return ok();
+}
+
+const char* transfer_last_error(void) { return g_last_error.c_str(); }
+
+int transfer_version(void) { return 100; }
+
+}  // extern "C"

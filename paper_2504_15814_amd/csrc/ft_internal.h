@@ -1,0 +1,116 @@
+// Internal types shared by the host-side operator builder, the C ABI and the
+// gfx950 kernels.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "facetransfer.h"
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ft {
+
+constexpr int kMaxP = 48;        // largest supported patch size
+constexpr int kAxisClasses = 5;  // tangential classes per axis (see axis_class)
+constexpr int kClasses = kAxisClasses * kAxisClasses;
+constexpr int kMaxStencil = 64;  // widest weight block (a 3rd-order fit uses <= 33)
+
+// Reference frame used by the builder and the kernels.
+//  * Normal coordinate n: interpolation counts coarse layers from the face
+//    into the coarse side (n >= 0 inside the coarse patch, n < 0 the coarse
+//    face's fine-side half); restriction counts fine layers into the fine
+//    side (n >= 0 the fine patch's inner half, n < 0 its halo).  Both
+//    destinations use the same n-mapping as their source buffer.
+//  * Tangential coordinates (b, c): cell index along the tangential axes b < c.
+// A block of weights serves every expansion cell whose tangential anchor
+// column lies in the same class along each axis.
+
+// Class of an anchor column m in [0, p): how far it is from either face edge,
+// saturated at two cells (all stencils reach at most two cells out).
+__host__ __device__ inline int axis_class(int m, int p) {
+  const int lo = m < 2 ? m : 2;
+  const int hi = (p - 1 - m) < 2 ? (p - 1 - m) : 2;
+  return lo < 2 ? lo : 4 - hi;
+}
+
+// Physical strides (in cells) of the normal and tangential axes of a face
+// buffer with normal axis a: cell = i0 + e0 * (i1 + e1 * i2).
+struct FaceStrides {
+  int sa, sb, sc;
+};
+__host__ __device__ inline FaceStrides face_strides(int a, int p, int k) {
+  FaceStrides s;
+  if (a == 0) {
+    s.sa = 1; s.sb = 2 * k; s.sc = 2 * k * p;
+  } else if (a == 1) {
+    s.sa = p; s.sb = 1; s.sc = 2 * k * p;
+  } else {
+    s.sa = p * p; s.sb = 1; s.sc = p;
+  }
+  return s;
+}
+
+// Buffer index along the normal of reference coordinate n: base + sign * n.
+// Interpolation: n counts into the coarse side, which is the - side (buffer
+// indices k-1, k-2, ...) when the fine patch lies on the + side (o < 3).
+// Restriction: n counts into the fine side.
+__host__ __device__ inline void normal_map(int direction, int o, int k, int* base, int* sign) {
+  const bool fine_plus = o < 3;
+  const bool count_minus = (direction == 0) ? fine_plus : !fine_plus;
+  *base = count_minus ? k - 1 : k;
+  *sign = count_minus ? -1 : 1;
+}
+
+// Packed stencil entry: normal coordinate (absolute) and tangential offsets
+// from the block's anchor column, each as a signed byte.
+__host__ __device__ inline int pack_point(int n, int db, int dc) {
+  return (n & 0xff) | ((db & 0xff) << 8) | ((dc & 0xff) << 16);
+}
+__host__ __device__ inline void unpack_point(int v, int* n, int* db, int* dc) {
+  *n = (int)(int8_t)(v & 0xff);
+  *db = (int)(int8_t)((v >> 8) & 0xff);
+  *dc = (int)(int8_t)((v >> 16) & 0xff);
+}
+
+// Kernel-side view of an operator (passed by value as a kernel argument).
+struct DevOp {
+  int direction, scheme, p, k;
+  int R;          // rows per expansion cell
+  int E;          // expansion cells per axis and subface (p / 3)
+  int copy_row;   // row that is an exact copy of a source cell, or -1
+  int copy_n;     // normal coordinate of that source cell (tangential = anchor)
+  int width[kClasses];  // stencil width per block (0 = class unused)
+  int start[kClasses];  // first stencil entry of the block
+  const int* stencil;   // packed points, [sum of widths]
+  const double* w64;    // weights, [(start + q) * R + r]
+  const float* w32;
+};
+
+// Host-side operator: the weight tables plus their device copies.
+struct HostBlock {
+  int width = 0;
+  std::vector<int> points;      // packed
+  std::vector<double> weights;  // [q * R + r]
+};
+
+}  // namespace ft
+
+struct ft_operator {
+  int direction, scheme, p, k, R, E, copy_row, copy_n;
+  ft::HostBlock blocks[ft::kClasses];
+  bool on_device = false;
+  int device = -1;
+  int* d_stencil = nullptr;
+  double* d_w64 = nullptr;
+  float* d_w32 = nullptr;
+  int* d_errors = nullptr;
+  ft::DevOp dev{};
+};
+
+namespace ft {
+// Builder (host): fills blocks[] of op for op->direction/scheme/p/k.
+// Returns an empty string on success, else a message.
+std::string build_tables(ft_operator* op);
+}  // namespace ft

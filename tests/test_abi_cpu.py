@@ -1,0 +1,151 @@
+"""C-ABI checks that need no GPU: the library loads and exports every
+declared symbol, host-side argument checks return the documented codes, and
+the host-built weight tables with their orientation maps equal the oracle's
+operators (maps bit-exact, weights to 1e-13 of the row's 1-norm)."""
+
+import ctypes
+import os
+import re
+from itertools import product
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_15814_amd import _lib, api
+from paper_2504_15814_amd.build import lib_path
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "facetransfer.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(lib_path()), reason="library not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_functions()
+    assert "interpolate_faces" in names and "restrict_faces" in names and "build_transfer_operator" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def test_version_and_empty_error():
+    assert api.transfer_version() == 100
+    assert isinstance(api.transfer_last_error(), str)
+
+
+@pytest.mark.parametrize(
+    "args,code",
+    [
+        ((2, 2, 9, 3), api.FT_ERR_INVALID),   # bad direction
+        ((0, 4, 9, 3), api.FT_ERR_INVALID),   # bad scheme
+        ((0, 2, 10, 3), api.FT_ERR_UNSUPPORTED),  # p not a multiple of 3
+        ((0, 2, 3, 3), api.FT_ERR_UNSUPPORTED),   # p too small
+        ((0, 2, 51, 3), api.FT_ERR_UNSUPPORTED),  # p too large
+        ((0, 2, 9, 1), api.FT_ERR_UNSUPPORTED),   # k = 1
+        ((0, 2, 9, 4), api.FT_ERR_UNSUPPORTED),   # k = 4
+    ],
+)
+def test_build_rejects_bad_arguments(args, code):
+    lib = _lib.load()
+    h = ctypes.c_void_p(123)
+    rc = lib.build_transfer_operator(*args, api.FT_BUILD_HOST_ONLY, ctypes.byref(h))
+    assert rc == code
+    assert h.value is None
+    assert api.transfer_last_error() != ""
+
+
+def test_build_rejects_null_out_and_bad_flags():
+    lib = _lib.load()
+    assert lib.build_transfer_operator(0, 2, 9, 3, 1, None) == api.FT_ERR_INVALID
+    h = ctypes.c_void_p()
+    assert lib.build_transfer_operator(0, 2, 9, 3, 8, ctypes.byref(h)) == api.FT_ERR_INVALID
+
+
+def test_apply_checks_happen_on_host():
+    """Every rejection below happens before any HIP call."""
+    lib = _lib.load()
+    op = api.build_transfer_operator(0, 2, 9, 3, api.FT_BUILD_HOST_ONLY)
+    rop = api.build_transfer_operator(1, 2, 9, 3, api.FT_BUILD_HOST_ONLY)
+    p = ctypes.c_void_p(16)
+    args = (1, p, p, p, p, 59, 0, p, 10**6, ctypes.c_void_p(32), 10**6, None)
+    assert lib.interpolate_faces(None, *args) == api.FT_ERR_INVALID
+    assert lib.interpolate_faces(rop.handle, *args) == api.FT_ERR_INVALID  # wrong direction
+    assert lib.restrict_faces(op.handle, *args) == api.FT_ERR_INVALID
+    assert lib.interpolate_faces(op.handle, *args) == api.FT_ERR_INVALID  # host-only operator
+    assert "host-only" in api.transfer_last_error()
+    n = ctypes.c_int64()
+    assert lib.transfer_operator_errors(op.handle, ctypes.byref(n), 0) == api.FT_ERR_INVALID
+    assert lib.transfer_operator_info(None, None, 0) == api.FT_ERR_INVALID
+    assert lib.transfer_operator_segment(op.handle, 6, 0, 0, None, None, None, ctypes.byref(n)) == api.FT_ERR_INVALID
+    assert lib.transfer_operator_segment(op.handle, 0, 9, 0, None, None, None, ctypes.byref(n)) == api.FT_ERR_INVALID
+    assert lib.destroy_transfer_operator(None) == api.FT_OK
+    op.destroy()
+    rop.destroy()
+
+
+def test_info_counts():
+    op = api.build_transfer_operator(0, 3, 9, 3, api.FT_BUILD_HOST_ONLY)
+    info = op.info()
+    assert info["rows_per_anchor"] == 27 and info["anchors"] == 9
+    assert info["blocks"] == 25 and 30 <= info["max_width"] <= 33
+    rop = api.build_transfer_operator(1, 3, 9, 3, api.FT_BUILD_HOST_ONLY)
+    assert rop.info()["rows_per_anchor"] == 3 and rop.info()["blocks"] == 9
+
+
+def _dense(op, o, s, p, k):
+    rows, cols, vals = op.segment(o, s)
+    ncell = 2 * k * p * p
+    D = np.zeros((ncell, ncell))
+    np.add.at(D, (rows, cols), vals)
+    return set(rows.tolist()), D
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+@pytest.mark.parametrize("p,k", [(6, 2), (6, 3), (9, 2), (9, 3), (12, 2), (12, 3)])
+def test_library_segments_equal_oracle(direction, scheme, p, k):
+    op = api.build_transfer_operator(direction, scheme, p, k, api.FT_BUILD_HOST_ONLY)
+    subfaces = range(9)
+    for o, s in product(range(6), subfaces):
+        rows_lib, D = _dense(op, o, s, p, k)
+        rows, W = oracle.transfer_operator(direction, scheme, p, k, o, s)
+        assert rows_lib == set(rows.tolist())  # destination map, exact
+        got = D[rows]
+        scale = np.abs(W).sum(axis=1)
+        err = (np.abs(got - W).max(axis=1) / scale).max()
+        assert err < 1e-13, (o, s, err)
+        # source map: every oracle weight above rounding level is present
+        big = np.abs(W) > 1e-12 * scale[:, None]
+        assert np.all(got[big] != 0.0)
+
+
+def test_copy_rows_are_unit_weights():
+    """Rows whose centres coincide hold a single weight of exactly 1."""
+    for direction, scheme in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3)):
+        op = api.build_transfer_operator(direction, scheme, 9, 3, api.FT_BUILD_HOST_ONLY)
+        rows, cols, vals = op.segment(1, 4)
+        ones = np.flatnonzero(vals == 1.0)
+        per_row = np.bincount(rows, minlength=rows.max() + 1)
+        singles = [r for r in np.unique(rows) if per_row[r] == 1]
+        assert len(singles) == 9
+        assert set(rows[ones]) >= set(singles)
+
+
+def test_apply_without_gpu_fails_cleanly():
+    """Building for the device on a machine without a GPU reports FT_ERR_HIP."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    rc = lib.build_transfer_operator(0, 2, 9, 3, 0, ctypes.byref(h))
+    assert rc == api.FT_ERR_HIP
+    assert h.value is None
