@@ -35,7 +35,22 @@ def parse():
     ap.add_argument("--cpu-faces", type=int, default=4000,
                     help="faces in the oracle's CPU-baseline sample (0 disables it)")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy(torch):
+    """A plain 2 GiB float64 device-to-device copy, five times: the bytes the
+    HBM counters report for it give their scale factor."""
+    n = 1 << 28
+    src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "reps": 5}))
 
 
 def algorithmic_bytes(op, orientation, subface, U, elem_bytes):
@@ -124,6 +139,10 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
 
     from paper_2504_15814_amd import api
     from paper_2504_15814_amd import workloads as wl

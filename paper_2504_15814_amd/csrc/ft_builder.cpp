@@ -283,14 +283,22 @@ std::string build_tables(ft_operator* op) {
       std::vector<Row> rows;
       std::string err;
       if (!block_rows(op, ab, ac, &rows, &err)) return err;
-      // Union of source cells with a nonzero weight, ordered (n, c, b).
+      // Union of source cells with a nonzero weight, ordered (n, c, b), except
+      // that the source of the exact-copy row (if any) comes first: the
+      // kernels take the copied value from the first loaded stencil point.
       std::map<std::tuple<int, int, int>, int> index;  // key (n, dc, db)
       for (auto& r : rows)
         for (auto& [cell, w] : r)
           if (w != 0.0L)
             index[{std::get<0>(cell), std::get<2>(cell) - ac, std::get<1>(cell) - ab}] = 0;
       int q = 0;
-      for (auto& kv : index) kv.second = q++;
+      const std::tuple<int, int, int> copy_key{op->copy_n, 0, 0};
+      if (op->copy_row >= 0) {
+        if (!index.count(copy_key)) return "internal: copy source missing from its block";
+        index[copy_key] = q++;
+      }
+      for (auto& kv : index)
+        if (!(op->copy_row >= 0 && kv.first == copy_key)) kv.second = q++;
       if (q > kMaxStencil) return "weight block wider than supported";
       blk.width = q;
       blk.points.resize(q);

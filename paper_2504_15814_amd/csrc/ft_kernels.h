@@ -25,8 +25,8 @@ struct LaunchArgs {
 // Tunable launch shape (schedules never change the per-output summation
 // order, so every shape gives bitwise identical results).
 struct LaunchConfig {
-  int waves_per_block = 4;  // 1..16
-  int xcd_remap = 1;
+  int waves_per_block = 4;  // 1..4
+  int xcd_remap = 0;
 };
 
 hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const LaunchConfig& cfg,
