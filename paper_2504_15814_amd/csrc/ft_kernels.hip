@@ -151,7 +151,10 @@ __global__ __launch_bounds__(256) void apply_kernel(
       } else {
         dcell = dst_cell0 + r * nstride;
       }
-      dp[(int64_t)dcell * U + u] = T(r == COPY ? copy_val : acc[r]);
+      // Streaming (non-temporal) stores: the written halo is not re-read by
+      // this launch, and keeping it out of L2 preserves the source
+      // footprints that neighbouring anchors of the same face re-read.
+      __builtin_nontemporal_store(T(r == COPY ? copy_val : acc[r]), &dp[(int64_t)dcell * U + u]);
     }
   }
 }
