@@ -69,6 +69,26 @@ def algorithmic_bytes(op, orientation, subface, U, elem_bytes):
     return int(sum(per[(o, s)] * counts[o, s] for o in range(6) for s in range(9)))
 
 
+def recorded_traffic(kernel_name):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) recorded for this kernel
+    in profiles/, or None if the kernel source changed since they were taken."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "apply_kernel_workload2.md")
+    src = os.path.join(ROOT, "paper_2504_15814_amd", "csrc", "ft_kernels.hip")
+    try:
+        text = open(prof).read()
+        block = text.split("```json")[1].split("```")[0]
+        rec = json.loads(block)
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if rec.get("kernel_source_sha256_16") != cur:
+            return None
+        k = rec["kernels"][f"f64/{kernel_name}"]
+        return int(k["read_bytes"] + k["write_bytes"])
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
 def run_steps(launches, steps, warmup, torch):
     """Time `steps` passes over `launches` (list of (name, fn)); per-launch
     durations come from events recorded on the launch stream."""
@@ -192,7 +212,7 @@ def main():
     dom = max(kernels, key=lambda kk: kernels[kk]["ms"])
     ach = kernels[dom]["GB/s"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom)}
     total_bytes = sum(v["alg_bytes"] for v in kernels.values())
 
     result = {
