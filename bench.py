@@ -174,7 +174,7 @@ def main():
     orient_np = batch.orientation.cpu().numpy()
     sub_np = batch.subface.cpu().numpy()
 
-    def make_launches(dtype):
+    def make_launches(dtype, mode=None):
         coarse_in = batch.coarse.to(dtype)
         fine_in = batch.fine.to(dtype)
         coarse_out = coarse_in.clone()
@@ -188,17 +188,17 @@ def main():
 
             def r(rop=rop):
                 api.restrict_faces(rop, batch.orientation, batch.subface, batch.coarse_offset,
-                                   batch.fine_offset, U, fine_in, coarse_out)
+                                   batch.fine_offset, U, fine_in, coarse_out, mode=mode)
 
             def i(iop=iop):
                 api.interpolate_faces(iop, batch.orientation, batch.subface, batch.coarse_offset,
-                                      batch.fine_offset, U, coarse_in, fine_out)
+                                      batch.fine_offset, U, coarse_in, fine_out, mode=mode)
 
             launches.append((f"restrict_{SCHEME_NAMES[scheme]}", r))
             launches.append((f"interpolate_{SCHEME_NAMES[scheme]}", i))
         return launches, ops, (coarse_out, fine_out)
 
-    launches, ops, _ = make_launches(torch.float64)
+    launches, ops, outs64 = make_launches(torch.float64)
     ms, kern_ms = run_steps(launches, args.steps, args.warmup, torch)
     produced = 3 * n * (9 * k * (p // 3) ** 2 + k * (p // 3) ** 2) * U
     value = produced / (ms * 1e-3)
@@ -236,16 +236,28 @@ def main():
     }
 
     if not args.no_mixed:
-        del launches
-        mlaunches, mops, _ = make_launches(torch.float32)
-        mms, mkern = run_steps(mlaunches, args.steps, args.warmup, torch)
-        result["mixed_f32"] = {
-            "value": produced / (mms * 1e-3),
-            "ms_per_step": mms,
-            "speedup_vs_f64": ms / mms,
-            "kernels_ms": {kk: round(v, 4) for kk, v in mkern.items()},
-        }
-        del mlaunches, mops
+        # Reference outputs of the last FP64 scheme (Taylor-3) for error reports.
+        ref_c, ref_f = outs64[0].clone(), outs64[1].clone()
+        del launches, outs64
+        result["mixed"] = {}
+        for label, mode in (("f32", api.FT_F32), ("bf16x3", api.FT_F32_BF16X3), ("bf16x6", api.FT_F32_BF16X6)):
+            mlaunches, mops, mouts = make_launches(torch.float32, mode)
+            mms, mkern = run_steps(mlaunches, args.steps, args.warmup, torch)
+            errs = {}
+            for nm, got, ref in (("interpolate_taylor3", mouts[1], ref_f), ("restrict_taylor3", mouts[0], ref_c)):
+                g = got.view(-1, U).double()
+                rr = ref.view(-1, U)
+                emax = (g - rr).abs().amax(dim=0) / rr.abs().amax(dim=0)
+                erms = (g - rr).pow(2).mean(dim=0).sqrt() / rr.pow(2).mean(dim=0).sqrt()
+                errs[nm] = {"max_rel": float(emax.max()), "rms_rel": float(erms.max())}
+            result["mixed"][label] = {
+                "value": produced / (mms * 1e-3),
+                "ms_per_step": mms,
+                "speedup_vs_f64": ms / mms,
+                "kernels_ms": {kk: round(v, 4) for kk, v in mkern.items()},
+                "err_vs_f64_gpu": errs,
+            }
+            del mlaunches, mops, mouts
 
     if args.cpu_faces > 0:
         result["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_faces, n), torch)

@@ -93,13 +93,26 @@ extern "C" {
 #define FT_TAYLOR2 2
 #define FT_TAYLOR3 3
 
-/* Element types of face buffers.
- * FT_F64: float64 storage, float64 arithmetic.
- * FT_F32: float32 storage; interpolation sums in float32 with float32
- *         weights, restriction sums in float64 (extrapolation weights have
- *         a large 1-norm, so cancellation decides the accuracy there). */
+/* Element types of face buffers and how the operator is applied.
+ * FT_F64:        float64 storage, float64 arithmetic.
+ * FT_F32:        float32 storage; interpolation sums in float32 with float32
+ *                weights on the vector ALUs, restriction sums in float64
+ *                (extrapolation weights have a large 1-norm, so cancellation
+ *                decides the accuracy there).
+ * FT_F32_BF16X3: float32 storage; interpolation on the matrix cores: weights
+ *                and data are split into bfloat16 parts (x = x0 + x1 + x2
+ *                exactly, W = W0 + W1 + W2) and W0 x0 + W0 x1 + W1 x0 is
+ *                accumulated in float32 (each dropped product is at most
+ *                2^-16 of |w x|: error <= about 3 * 2^-16 of sum |w x| per
+ *                output).  Restriction as FT_F32.
+ * FT_F32_BF16X6: as FT_F32_BF16X3 plus the compensating products
+ *                W0 x2 + W1 x1 + W2 x0 of the split residuals (dropped terms
+ *                <= 3 * 2^-24 of sum |w x|, i.e. float32 rounding level).
+ *                Restriction as FT_F32. */
 #define FT_F64 0
 #define FT_F32 1
+#define FT_F32_BF16X3 2
+#define FT_F32_BF16X6 3
 
 /* Build flags. */
 #define FT_BUILD_HOST_ONLY 1 /* build the weight tables on the host only; the
@@ -136,7 +149,8 @@ int destroy_transfer_operator(ft_operator* op);
  * fine_offset   : device int64[n_faces], element offset of each fine face
  *                 buffer inside `fine`.
  * unknowns      : U, unknowns per cell (AoS, innermost).
- * dtype         : FT_F64 or FT_F32, element type of both buffers.
+ * dtype         : FT_F64, FT_F32, FT_F32_BF16X3 or FT_F32_BF16X6 (the last
+ *                 three store float32).
  * coarse        : device, coarse_elems elements, read only.
  * fine          : device, fine_elems elements; only the halo (coarse-side)
  *                 half of each referenced fine face buffer is written.

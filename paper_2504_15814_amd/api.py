@@ -15,7 +15,7 @@ from . import _lib
 FT_OK, FT_ERR_INVALID, FT_ERR_UNSUPPORTED, FT_ERR_HIP, FT_ERR_NOMEM = 0, 1, 2, 3, 4
 FT_INTERPOLATE, FT_RESTRICT = 0, 1
 FT_DLINEAR, FT_TAYLOR2, FT_TAYLOR3 = 1, 2, 3
-FT_F64, FT_F32 = 0, 1
+FT_F64, FT_F32, FT_F32_BF16X3, FT_F32_BF16X6 = 0, 1, 2, 3
 FT_BUILD_HOST_ONLY = 1
 
 _DTYPES = {torch.float64: FT_F64, torch.float32: FT_F32}
@@ -116,29 +116,45 @@ def _descriptors(orientation, subface, coarse_offset, fine_offset):
     return n
 
 
-def interpolate_faces(op, orientation, subface, coarse_offset, fine_offset, unknowns, coarse, fine, stream=None):
-    """Fill the halo half of every fine face buffer from its coarse face."""
-    n = _descriptors(orientation, subface, coarse_offset, fine_offset)
-    if coarse.dtype != fine.dtype or coarse.dtype not in _DTYPES:
+def _mode(a, b, mode):
+    """The C dtype code for tensors a, b: float64 -> FT_F64; float32 ->
+    FT_F32 unless a split-bfloat16 mode is requested."""
+    if a.dtype != b.dtype or a.dtype not in _DTYPES:
         raise TypeError("coarse and fine must share dtype float64 or float32")
+    if mode is None:
+        return _DTYPES[a.dtype]
+    if a.dtype == torch.float64 and mode != FT_F64:
+        raise TypeError("float64 buffers only support FT_F64")
+    if a.dtype == torch.float32 and mode not in (FT_F32, FT_F32_BF16X3, FT_F32_BF16X6):
+        raise TypeError("float32 buffers support FT_F32, FT_F32_BF16X3 and FT_F32_BF16X6")
+    return mode
+
+
+def interpolate_faces(op, orientation, subface, coarse_offset, fine_offset, unknowns, coarse, fine,
+                      stream=None, mode=None):
+    """Fill the halo half of every fine face buffer from its coarse face.
+    `mode` selects the float32 application (FT_F32, FT_F32_BF16X3,
+    FT_F32_BF16X6); by default it follows the tensors' dtype."""
+    n = _descriptors(orientation, subface, coarse_offset, fine_offset)
+    dt = _mode(coarse, fine, mode)
     _check(
         _lib.load().interpolate_faces(
             op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
-            unknowns, _DTYPES[coarse.dtype], _ptr(coarse), coarse.numel(), _ptr(fine), fine.numel(),
+            unknowns, dt, _ptr(coarse), coarse.numel(), _ptr(fine), fine.numel(),
             _stream_ptr(stream)),
         "interpolate_faces",
     )
 
 
-def restrict_faces(op, orientation, subface, coarse_offset, fine_offset, unknowns, fine, coarse, stream=None):
+def restrict_faces(op, orientation, subface, coarse_offset, fine_offset, unknowns, fine, coarse,
+                   stream=None, mode=None):
     """Fill each fine face's segment of its coarse face's fine-side half."""
     n = _descriptors(orientation, subface, coarse_offset, fine_offset)
-    if coarse.dtype != fine.dtype or coarse.dtype not in _DTYPES:
-        raise TypeError("coarse and fine must share dtype float64 or float32")
+    dt = _mode(fine, coarse, mode)
     _check(
         _lib.load().restrict_faces(
             op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
-            unknowns, _DTYPES[fine.dtype], _ptr(fine), fine.numel(), _ptr(coarse), coarse.numel(),
+            unknowns, dt, _ptr(fine), fine.numel(), _ptr(coarse), coarse.numel(),
             _stream_ptr(stream)),
         "restrict_faces",
     )

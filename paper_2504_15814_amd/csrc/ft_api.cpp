@@ -30,6 +30,53 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(FT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Round a float to bfloat16 (round to nearest even); NaN stays NaN.
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// MFMA A-operand table of an interpolation operator: every weight split into
+// three bfloat16 parts, zero for padding rows / stencil points and for the
+// exact-copy row.  Empty if a block is wider than the MFMA path supports.
+std::vector<uint16_t> bf16_table(const ft_operator* op) {
+  std::vector<uint16_t> t;
+  if (op->direction != FT_INTERPOLATE) return t;
+  for (int c = 0; c < ft::kClasses; ++c)
+    if (op->blocks[c].width > ft::kMfmaSteps * ft::kMfmaK) return t;
+  t.assign((size_t)ft::mfma_a_index(ft::kClasses, 0, 0, 0), 0);
+  for (int c = 0; c < ft::kClasses; ++c) {
+    const ft::HostBlock& b = op->blocks[c];
+    for (int st = 0; st < ft::kMfmaSteps; ++st)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int m = lane % 32;
+        for (int i = 0; i < 8; ++i) {
+          const int q = ft::kMfmaK * st + 8 * (lane / 32) + i;
+          if (m >= op->R || m == op->copy_row || q >= b.width) continue;
+          const double w = b.weights[(size_t)q * op->R + m];
+          const uint16_t w0 = bf16_rne((float)w);
+          const double r1 = w - bf16_value(w0);
+          const uint16_t w1 = bf16_rne((float)r1);
+          const uint16_t w2 = bf16_rne((float)(r1 - bf16_value(w1)));
+          const uint16_t parts[3] = {w0, w1, w2};
+          for (int part = 0; part < ft::kBf16Parts; ++part)
+            t[(size_t)ft::mfma_a_index(c, st, part, lane) + i] = parts[part];
+        }
+      }
+  }
+  return t;
+}
+
 void free_device(ft_operator* op) {
   if (!op->on_device) return;
   int prev = -1;
@@ -38,11 +85,13 @@ void free_device(ft_operator* op) {
   if (op->d_stencil) (void)hipFree(op->d_stencil);
   if (op->d_w64) (void)hipFree(op->d_w64);
   if (op->d_w32) (void)hipFree(op->d_w32);
+  if (op->d_wbf16) (void)hipFree(op->d_wbf16);
   if (op->d_errors) (void)hipFree(op->d_errors);
   if (prev >= 0) (void)hipSetDevice(prev);
   op->d_stencil = nullptr;
   op->d_w64 = nullptr;
   op->d_w32 = nullptr;
+  op->d_wbf16 = nullptr;
   op->d_errors = nullptr;
   op->on_device = false;
 }
@@ -69,6 +118,7 @@ int upload(ft_operator* op) {
   }
   w32.resize(w64.size());
   for (size_t i = 0; i < w64.size(); ++i) w32[i] = (float)w64[i];
+  const std::vector<uint16_t> wbf = bf16_table(op);
   if (pts.empty()) return fail(FT_ERR_INVALID, "operator has no weights");
   hipError_t e = hipGetDevice(&op->device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -76,7 +126,9 @@ int upload(ft_operator* op) {
   if ((e = hipMalloc(&op->d_stencil, pts.size() * sizeof(int))) != hipSuccess ||
       (e = hipMalloc(&op->d_w64, w64.size() * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&op->d_w32, w32.size() * sizeof(float))) != hipSuccess ||
-      (e = hipMalloc(&op->d_errors, sizeof(int))) != hipSuccess) {
+      (e = hipMalloc(&op->d_errors, sizeof(int))) != hipSuccess ||
+      (!wbf.empty() &&
+       (e = hipMalloc(&op->d_wbf16, wbf.size() * sizeof(uint16_t))) != hipSuccess)) {
     free_device(op);
     return e == hipErrorOutOfMemory ? fail(FT_ERR_NOMEM, "device allocation failed")
                                     : hip_fail(e, "hipMalloc");
@@ -87,13 +139,16 @@ int upload(ft_operator* op) {
           hipSuccess ||
       (e = hipMemcpy(op->d_w32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice)) !=
           hipSuccess ||
-      (e = hipMemset(op->d_errors, 0, sizeof(int))) != hipSuccess) {
+      (e = hipMemset(op->d_errors, 0, sizeof(int))) != hipSuccess ||
+      (!wbf.empty() && (e = hipMemcpy(op->d_wbf16, wbf.data(), wbf.size() * sizeof(uint16_t),
+                                      hipMemcpyHostToDevice)) != hipSuccess)) {
     free_device(op);
     return hip_fail(e, "uploading operator tables");
   }
   d.stencil = op->d_stencil;
   d.w64 = op->d_w64;
   d.w32 = op->d_w32;
+  d.wbf16 = op->d_wbf16;
   return FT_OK;
 }
 
@@ -108,7 +163,10 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
   if (!op->on_device) return fail(FT_ERR_INVALID, "operator was built host-only");
   if (n_faces < 0) return fail(FT_ERR_INVALID, "n_faces < 0");
   if (unknowns < 1 || unknowns > 4096) return fail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
-  if (dtype != FT_F64 && dtype != FT_F32) return fail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return fail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (direction == FT_INTERPOLATE && (dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6) &&
+      op->on_device && !op->d_wbf16)
+    return fail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
   if (src_elems < 0 || dst_elems < 0) return fail(FT_ERR_INVALID, "negative buffer size");
   if (n_faces == 0) return FT_OK;
   if (!orientation || !subface || !so || !dof || !src || !dst)
@@ -184,7 +242,12 @@ int interpolate_faces(const ft_operator* op, int64_t n_faces, const int8_t* orie
   if (rc != FT_OK || n_faces == 0) return rc == FT_OK ? ok() : rc;
   ft::LaunchArgs la{n_faces, orientation, subface, coarse_offset, fine_offset, unknowns, dtype,
                     coarse, coarse_elems, fine, fine_elems, op->d_errors};
-  hipError_t e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
+  hipError_t e;
+  if (dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6)
+    e = ft::launch_interp_mfma(op, la, ft::LaunchConfig(), dtype == FT_F32_BF16X6 ? 6 : 3,
+                               (hipStream_t)stream);
+  else
+    e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "interpolate_faces launch");
   return ok();
 }

@@ -86,7 +86,22 @@ struct DevOp {
   const int* stencil;   // packed points, [sum of widths]
   const double* w64;    // weights, [(start + q) * R + r]
   const float* w32;
+  // Interpolation only: the weights split into three bfloat16 parts
+  // (W = W0 + W1 + W2 to ~2^-27 relative), laid out as MFMA A operands:
+  // [class][k-step][part][lane][8], see mfma_a_index().
+  const uint16_t* wbf16;
 };
+
+// MFMA v_mfma_f32_32x32x16_bf16 operand layout (lane l of a wave):
+//   A (32 x 16): lane l holds A[l % 32][8 * (l / 32) + i], i = 0..7
+//   B (16 x 32): lane l holds B[8 * (l / 32) + i][l % 32]
+//   D (32 x 32): register v of lane l holds D[8 * (v / 4) + 4 * (l / 32) + v % 4][l % 32]
+constexpr int kMfmaK = 16;       // stencil points per MFMA k-step
+constexpr int kMfmaSteps = 3;    // k-steps per block: stencils up to 48 points
+constexpr int kBf16Parts = 3;
+__host__ __device__ inline int64_t mfma_a_index(int cls, int step, int part, int lane) {
+  return ((((int64_t)cls * kMfmaSteps + step) * kBf16Parts + part) * 64 + lane) * 8;
+}
 
 // Host-side operator: the weight tables plus their device copies.
 struct HostBlock {
@@ -105,6 +120,7 @@ struct ft_operator {
   int* d_stencil = nullptr;
   double* d_w64 = nullptr;
   float* d_w32 = nullptr;
+  uint16_t* d_wbf16 = nullptr;
   int* d_errors = nullptr;
   ft::DevOp dev{};
 };

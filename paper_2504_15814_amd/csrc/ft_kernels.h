@@ -32,4 +32,8 @@ struct LaunchConfig {
 hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const LaunchConfig& cfg,
                         hipStream_t stream);
 
+// Float32 interpolation on the matrix cores with 3 or 6 split-bfloat16 terms.
+hipError_t launch_interp_mfma(const ft_operator* op, const LaunchArgs& la,
+                              const LaunchConfig& cfg, int terms, hipStream_t stream);
+
 }  // namespace ft

@@ -222,6 +222,7 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
   g.waves_per_block = cfg.waves_per_block;
   g.xcd_remap = cfg.xcd_remap;
   if (la.dtype == FT_F64) return launch_typed<double, double>(op, g, la, stream);
+  // FT_F32 and (for restriction) the split-bfloat16 modes: float32 storage.
   return launch_typed<float, float>(op, g, la, stream);
 }
 

@@ -18,7 +18,7 @@ Workloads (all seeds are 15814 + workload number; draw order is fixed below):
 2  20,000 faces, p = 9, k = 3, U = 59; o, s uniform; per unknown 8 Gaussian
    bumps (amplitude N(0,1), centre U[0,1]^3, width U[0.2, 1]) plus
    N(0, 1e-3^2) noise on every stored value.
-3  workload 2 with unknown u scaled by 10^(-6 + 9 u / 58).
+3  workload 2 with unknown u (field and noise) scaled by 10^(-6 + 9 u / 58).
 4  50,000 faces: p in {6, 9, 12} at 30/50/20 %, k in {2, 3}, scheme and
    direction uniform, U = 59, fields as workload 2.
 Faces sit on a grid of 9^3 coarse patches (h_c = 1/81, h_f = 1/243).
@@ -176,9 +176,10 @@ def face_origins(gen, orientation, p):
     return cell
 
 
-def fill_buffers(batch, field_fn, noise_sigma=0.0, gen=None, chunk=2048):
+def fill_buffers(batch, field_fn, noise_sigma=0.0, gen=None, chunk=2048, noise_scale=None):
     """Sample field_fn at every cell centre of every face (both buffers), add
-    iid N(0, noise_sigma^2) noise, and store into batch.coarse / batch.fine."""
+    iid N(0, noise_sigma^2) noise (times noise_scale[u] per unknown if given),
+    and store into batch.coarse / batch.fine."""
     p, k, U = batch.p, batch.k, batch.U
     dev = batch.coarse.device
     ncell = 2 * k * p * p
@@ -204,8 +205,14 @@ def fill_buffers(batch, field_fn, noise_sigma=0.0, gen=None, chunk=2048):
         vc = field_fn(pos_c.reshape(-1, 3)).reshape(f1 - f0, E)
         vf = field_fn(pos_f.reshape(-1, 3)).reshape(f1 - f0, E)
         if noise_sigma:
-            vc += noise_sigma * torch.randn(vc.shape, generator=noise_gen, dtype=torch.float64, device=dev)
-            vf += noise_sigma * torch.randn(vf.shape, generator=noise_gen, dtype=torch.float64, device=dev)
+            nc = noise_sigma * torch.randn(vc.shape, generator=noise_gen, dtype=torch.float64, device=dev)
+            nf_ = noise_sigma * torch.randn(vf.shape, generator=noise_gen, dtype=torch.float64, device=dev)
+            if noise_scale is not None:
+                sc = noise_scale.to(dev).repeat(ncell)[None, :]
+                nc *= sc
+                nf_ *= sc
+            vc += nc
+            vf += nf_
         if contiguous:
             cview[f0 * E : f1 * E] = vc.reshape(-1).to(cview.dtype)
             fview[f0 * E : f1 * E] = vf.reshape(-1).to(fview.dtype)
@@ -250,7 +257,7 @@ def uniform_faces(n, p, k, U, seed, device="cpu", dtype=torch.float64, scaled=Fa
     origin = face_origins(gen, orient, p)
     fieldfn = bump_field(gen, U, scaled=scaled)
     batch = _contiguous_batch(orient, sub, p, k, U, dtype, device, origin)
-    fill_buffers(batch, fieldfn, noise_sigma=noise, gen=gen)
+    fill_buffers(batch, fieldfn, noise_sigma=noise, gen=gen, noise_scale=fieldfn.scale)
     return batch
 
 

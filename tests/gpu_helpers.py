@@ -31,7 +31,7 @@ def written_mask(direction, scheme, p, k, U, orientation, subface, dst_offset, d
     return mask, copy
 
 
-def run_gpu(direction, scheme, batch, dtype=torch.float64, op=None):
+def run_gpu(direction, scheme, batch, dtype=torch.float64, op=None, mode=None):
     """Apply the HIP path; returns (destination after the call as float64
     numpy, source as float64 numpy, destination before the call)."""
     dev = batch.coarse.device
@@ -43,13 +43,13 @@ def run_gpu(direction, scheme, batch, dtype=torch.float64, op=None):
         dst = torch.full_like(fine, SENTINEL)
         before = dst.clone()
         api.interpolate_faces(op, batch.orientation, batch.subface, batch.coarse_offset,
-                              batch.fine_offset, batch.U, coarse, dst)
+                              batch.fine_offset, batch.U, coarse, dst, mode=mode)
         src = coarse
     else:
         dst = torch.full_like(coarse, SENTINEL)
         before = dst.clone()
         api.restrict_faces(op, batch.orientation, batch.subface, batch.coarse_offset,
-                           batch.fine_offset, batch.U, fine, dst)
+                           batch.fine_offset, batch.U, fine, dst, mode=mode)
         src = fine
     torch.cuda.synchronize(dev)
     assert op.errors() == 0
@@ -92,3 +92,21 @@ def check_parity(direction, scheme, batch, dtype=torch.float64, tol=1e-12, faces
     # exact-copy rows are bit-exact
     assert np.array_equal(got[copy], want[copy])
     return emax, erms
+
+
+def abs_weighted_sums(direction, scheme, batch, src, dst_len, faces=None):
+    """Per destination element, sum_q |w_q x_q| from the oracle's operators
+    (the scale of the rounding error of any evaluation order)."""
+    out = np.zeros(dst_len)
+    o = batch.orientation.cpu().numpy()
+    s = batch.subface.cpu().numpy()
+    so = (batch.coarse_offset if direction == 0 else batch.fine_offset).cpu().numpy()
+    do = (batch.fine_offset if direction == 0 else batch.coarse_offset).cpu().numpy()
+    U = batch.U
+    ncell = 2 * batch.k * batch.p * batch.p
+    for f in (range(len(o)) if faces is None else faces):
+        rows, W = oracle.transfer_operator(direction, scheme, batch.p, batch.k, int(o[f]), int(s[f]))
+        x = np.abs(src[int(so[f]): int(so[f]) + ncell * U].reshape(ncell, U))
+        y = out[int(do[f]): int(do[f]) + ncell * U].reshape(ncell, U)
+        y[rows] = np.abs(W) @ x
+    return out

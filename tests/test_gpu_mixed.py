@@ -1,0 +1,98 @@
+"""Mixed-precision forms (float32 storage) against the FP64 oracle.
+
+Per element the error of a float32 evaluation is bounded by c * sum_q |w_q x_q|
+(the magnitude every rounding scales with): FT_F32 accumulates <= 33 products
+with float32 weights, c = (width + 2) 2^-24.  A bfloat16 rounding has
+relative error <= 2^-8, so with x = x0 + x1 + x2 and W = W0 + W1 + W2
+(|x1| <= 2^-8 |x|, |x2| <= 2^-16 |x|, likewise for W): FT_F32_BF16X3 drops
+W0x2 + W1x1 + W2x0 (each <= 2^-16 |w x|) and rounds 9 MFMA accumulations,
+c = 3 2^-16 + 9 2^-24; FT_F32_BF16X6 keeps them, dropping W1x2 + W2x1 + W2x2
+and the weight split residual (<= 3 2^-24 |w x|) with 18 accumulations,
+c = 21 2^-24.  The oracle runs in
+float64 on the same float32 inputs (kernel error); the end-to-end error
+against float64 data is reported per unknown for the precision workload.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_15814_amd import api
+from paper_2504_15814_amd import workloads as wl
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+C = {api.FT_F32: 35 * 2.0**-24, api.FT_F32_BF16X3: 3 * 2.0**-16 + 9 * 2.0**-24,
+     api.FT_F32_BF16X6: 21 * 2.0**-24}
+EMAX = {api.FT_F32: 1e-6, api.FT_F32_BF16X3: 2e-4, api.FT_F32_BF16X6: 2e-6}
+MODES = [api.FT_F32, api.FT_F32_BF16X3, api.FT_F32_BF16X6]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gh.require_gpu()
+
+
+@pytest.fixture(scope="module")
+def b59(dev):
+    return wl.uniform_faces(120, 9, 3, 59, seed=4242, device=dev)
+
+
+def check_mode(batch, scheme, mode, faces=None):
+    got, src, before = gh.run_gpu(0, scheme, batch, torch.float32, mode=mode)
+    want, (o, s, doff) = gh.run_oracle(0, scheme, batch, src, before, faces)
+    mask, copy = gh.written_mask(0, scheme, batch.p, batch.k, batch.U, o, s, doff, len(got))
+    scale = gh.abs_weighted_sums(0, scheme, batch, src, len(got), faces)
+    err = np.abs(got - want)
+    bound = C[mode] * scale + 2.0**-24 * np.abs(want)
+    assert np.all(err[mask] <= bound[mask]), float(np.max(err[mask] / np.maximum(bound[mask], 1e-300)))
+    assert np.array_equal(got[copy], want[copy])
+    if faces is None:
+        assert np.array_equal(got[~mask], before[~mask])
+    return gh.rel_errors(got, want, mask, batch.U)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+def test_interpolation_modes_within_bound(b59, scheme, mode):
+    emax, _ = check_mode(b59, scheme, mode)
+    assert emax.max() < EMAX[mode]
+
+
+@pytest.mark.parametrize("p,k", [(6, 2), (6, 3), (12, 2), (12, 3)])
+@pytest.mark.parametrize("U", [7, 33, 64, 70])
+def test_matrix_core_path_shapes(dev, p, k, U):
+    batch = wl.uniform_faces(20, p, k, U, seed=77 + p + k + U, device=dev)
+    for scheme in (2, 3):
+        check_mode(batch, scheme, api.FT_F32_BF16X6)
+    check_mode(batch, 1, api.FT_F32_BF16X3)
+
+
+def test_restriction_modes_share_the_float32_path(b59):
+    outs = []
+    for mode in MODES:
+        got, _, _ = gh.run_gpu(1, 3, b59, torch.float32, mode=mode)
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.fixture(scope="module")
+def w3(dev):
+    return wl.workload3(n_faces=2000, device=dev)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_precision_workload_per_unknown_errors(w3, mode):
+    """Unknowns scaled 1e-6 .. 1e3, third order: per-unknown relative errors
+    against the oracle on the same float32 inputs stay scale-free, and the
+    end-to-end error against float64 data is dominated by input rounding."""
+    faces = np.arange(0, w3.n, 10)
+    emax, erms = check_mode(w3, 3, mode, faces=faces)
+    assert emax.max() < EMAX[mode]
+    # end to end: float32 result vs float64 GPU path on float64 data
+    got32, _, _ = gh.run_gpu(0, 3, w3, torch.float32, mode=mode)
+    got64, _, _ = gh.run_gpu(0, 3, w3, torch.float64)
+    mask = got64 != gh.SENTINEL
+    e2e, _ = gh.rel_errors(got32, got64, mask, w3.U)
+    assert e2e.max() < EMAX[mode] + 1e-6
