@@ -194,6 +194,74 @@ int transfer_operator_segment(const ft_operator* op, int orientation, int subfac
                               int64_t capacity, int64_t* rows, int64_t* cols, double* vals,
                               int64_t* n_entries);
 
+/* ---------------------------------------------------------------------------
+ * Plans: uneven mixes in one launch
+ * ---------------------------------------------------------------------------
+ * A plan groups batches of hanging faces that use different operators
+ * (direction, scheme, p, k) over one coarse and one fine buffer, with one
+ * element type and one unknown count, and runs them as one persistent
+ * launch: a fixed grid of waves walks all (face, anchor) work items.  With
+ * FT_PLAN_RESTRICT_FIRST every restriction batch completes before any
+ * interpolation batch starts (two launches), as one time step needs when
+ * the interpolated faces read coarse data that the restriction writes
+ * (Section 2: halos are refreshed before the compute kernel).  Without it,
+ * all batches must be independent (no face writes what another reads). */
+#define FT_PLAN_RESTRICT_FIRST 1
+
+typedef struct ft_plan ft_plan;
+typedef struct ft_graph ft_graph;
+
+/* One batch of a plan (host struct; the arrays it points to are DEVICE
+ * memory, laid out as for interpolate_faces / restrict_faces). */
+typedef struct ft_plan_batch {
+  const ft_operator* op;
+  int64_t n_faces;
+  const int8_t* orientation;
+  const int8_t* subface;
+  const int64_t* coarse_offset;
+  const int64_t* fine_offset;
+} ft_plan_batch;
+
+/* Build a plan over n_batches batches (the batches[] array is copied; the
+ * device arrays and buffers must stay valid while the plan is used).
+ * dtype as for interpolate_faces; restriction batches of the FT_F32_BF16X*
+ * types run as FT_F32.  The schedule starts at a default and can be tuned
+ * with transfer_plan_autotune.  Allocates a small device table.
+ * Errors: FT_ERR_INVALID (null pointers, n_batches < 1, operators of another
+ * device), FT_ERR_UNSUPPORTED (dtype, unknowns), FT_ERR_NOMEM, FT_ERR_HIP. */
+int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknowns, int dtype,
+                        void* coarse, int64_t coarse_elems, void* fine, int64_t fine_elems,
+                        int flags, ft_plan** out);
+
+/* Run the plan asynchronously on `stream` (no allocation, no host
+ * synchronisation: capturable). */
+int run_transfer_plan(const ft_plan* plan, void* stream);
+
+/* Schedule of a plan, packed as waves_per_block | blocks_per_cu << 8 |
+ * xcd_remap << 16 | heavy_first << 17 (waves_per_block in {1, 2, 4},
+ * blocks_per_cu in 1..64).  Every schedule computes bitwise identical
+ * results (each output's summation order is fixed by the operator). */
+int transfer_plan_set_schedule(ft_plan* plan, int64_t schedule);
+int transfer_plan_get_schedule(const ft_plan* plan, int64_t* schedule);
+
+/* Autotuner: run the plan `reps` times under each candidate schedule (after
+ * one warm-up run), time it with HIP events on `stream`, keep the fastest,
+ * and report it and its mean time in milliseconds.  The runs write the
+ * plan's outputs like run_transfer_plan.  Synchronises the stream. */
+int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_schedule,
+                           double* best_ms);
+
+int destroy_transfer_plan(ft_plan* plan);
+
+/* Capture `steps` consecutive runs of the plan into one HIP graph on a
+ * library-owned stream and instantiate it. */
+int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out);
+
+/* Launch a captured graph on `stream`. */
+int transfer_graph_launch(const ft_graph* graph, void* stream);
+
+int destroy_transfer_graph(ft_graph* graph);
+
 /* Read (and optionally reset) the operator's device count of skipped faces.
  * Synchronises the device; not for use inside graph capture. */
 int transfer_operator_errors(const ft_operator* op, int64_t* n_skipped, int reset);

@@ -15,6 +15,20 @@ c_int64_p = ctypes.POINTER(ctypes.c_int64)
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_void_p = ctypes.c_void_p
 
+
+class PlanBatch(ctypes.Structure):
+    """ft_plan_batch"""
+
+    _fields_ = [
+        ("op", ctypes.c_void_p),
+        ("n_faces", ctypes.c_int64),
+        ("orientation", ctypes.c_void_p),
+        ("subface", ctypes.c_void_p),
+        ("coarse_offset", ctypes.c_void_p),
+        ("fine_offset", ctypes.c_void_p),
+    ]
+
+
 # name -> (restype, argtypes); mirrors include/facetransfer.h
 SIGNATURES = {
     "build_transfer_operator": (
@@ -38,6 +52,20 @@ SIGNATURES = {
         [c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64, c_int64_p, c_int64_p, c_double_p, c_int64_p],
     ),
     "transfer_operator_errors": (ctypes.c_int, [c_void_p, c_int64_p, ctypes.c_int]),
+    "build_transfer_plan": (
+        ctypes.c_int,
+        [ctypes.POINTER(PlanBatch), ctypes.c_int, ctypes.c_int, ctypes.c_int, c_void_p, ctypes.c_int64,
+         c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(c_void_p)],
+    ),
+    "run_transfer_plan": (ctypes.c_int, [c_void_p, c_void_p]),
+    "transfer_plan_set_schedule": (ctypes.c_int, [c_void_p, ctypes.c_int64]),
+    "transfer_plan_get_schedule": (ctypes.c_int, [c_void_p, c_int64_p]),
+    "transfer_plan_autotune": (
+        ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int, c_int64_p, ctypes.POINTER(ctypes.c_double)]),
+    "destroy_transfer_plan": (ctypes.c_int, [c_void_p]),
+    "transfer_plan_capture": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(c_void_p)]),
+    "transfer_graph_launch": (ctypes.c_int, [c_void_p, c_void_p]),
+    "destroy_transfer_graph": (ctypes.c_int, [c_void_p]),
     "transfer_last_error": (ctypes.c_char_p, []),
     "transfer_version": (ctypes.c_int, []),
 }

@@ -166,3 +166,121 @@ def transfer_last_error():
 
 def transfer_version():
     return _lib.load().transfer_version()
+
+
+# ---------------------------------------------------------------------------
+# Plans and graphs
+# ---------------------------------------------------------------------------
+FT_PLAN_RESTRICT_FIRST = 1
+
+
+def pack_schedule(waves_per_block=4, blocks_per_cu=8, xcd_remap=0, heavy_first=0):
+    return waves_per_block | (blocks_per_cu << 8) | (xcd_remap << 16) | (heavy_first << 17)
+
+
+def unpack_schedule(s):
+    return {"waves_per_block": s & 0xFF, "blocks_per_cu": (s >> 8) & 0xFF,
+            "xcd_remap": (s >> 16) & 1, "heavy_first": (s >> 17) & 1}
+
+
+class TransferPlan:
+    """Owns an ft_plan.  batches: list of (operator, orientation, subface,
+    coarse_offset, fine_offset) with device descriptor tensors; the tensors
+    and buffers are kept alive by the plan."""
+
+    def __init__(self, handle, keepalive):
+        self._h = handle
+        self._keep = keepalive
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("plan already destroyed")
+        return self._h
+
+    def run(self, stream=None):
+        run_transfer_plan(self, stream)
+
+    @property
+    def schedule(self):
+        v = ctypes.c_int64()
+        _check(_lib.load().transfer_plan_get_schedule(self.handle, ctypes.byref(v)), "transfer_plan_get_schedule")
+        return v.value
+
+    @schedule.setter
+    def schedule(self, value):
+        _check(_lib.load().transfer_plan_set_schedule(self.handle, int(value)), "transfer_plan_set_schedule")
+
+    def autotune(self, reps=3, stream=None):
+        return transfer_plan_autotune(self, reps, stream)
+
+    def capture(self, steps=1):
+        return transfer_plan_capture(self, steps)
+
+    def destroy(self):
+        if self._h:
+            _lib.load().destroy_transfer_plan(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class TransferGraph:
+    def __init__(self, handle, plan):
+        self._h = handle
+        self._plan = plan
+
+    def launch(self, stream=None):
+        transfer_graph_launch(self, stream)
+
+    def destroy(self):
+        if self._h:
+            _lib.load().destroy_transfer_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def build_transfer_plan(batches, unknowns, coarse, fine, mode=None, flags=0):
+    dt = _mode(coarse, fine, mode)
+    arr = (_lib.PlanBatch * len(batches))()
+    keep = [coarse, fine]
+    for i, (op, o, s, co, fo) in enumerate(batches):
+        n = _descriptors(o, s, co, fo)
+        arr[i] = _lib.PlanBatch(op.handle, n, o.data_ptr(), s.data_ptr(), co.data_ptr(), fo.data_ptr())
+        keep.extend([op, o, s, co, fo])
+    h = ctypes.c_void_p()
+    _check(_lib.load().build_transfer_plan(arr, len(batches), unknowns, dt, _ptr(coarse), coarse.numel(),
+                                           _ptr(fine), fine.numel(), flags, ctypes.byref(h)),
+           "build_transfer_plan")
+    return TransferPlan(h.value, keep)
+
+
+def run_transfer_plan(plan, stream=None):
+    _check(_lib.load().run_transfer_plan(plan.handle, _stream_ptr(stream)), "run_transfer_plan")
+
+
+def transfer_plan_autotune(plan, reps=3, stream=None):
+    best = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(_lib.load().transfer_plan_autotune(plan.handle, _stream_ptr(stream), reps, ctypes.byref(best),
+                                              ctypes.byref(ms)), "transfer_plan_autotune")
+    return best.value, ms.value
+
+
+def transfer_plan_capture(plan, steps=1):
+    h = ctypes.c_void_p()
+    _check(_lib.load().transfer_plan_capture(plan.handle, steps, ctypes.byref(h)), "transfer_plan_capture")
+    return TransferGraph(h.value, plan)
+
+
+def transfer_graph_launch(graph, stream=None):
+    _check(_lib.load().transfer_graph_launch(graph._h, _stream_ptr(stream)), "transfer_graph_launch")

@@ -86,12 +86,14 @@ void free_device(ft_operator* op) {
   if (op->d_w64) (void)hipFree(op->d_w64);
   if (op->d_w32) (void)hipFree(op->d_w32);
   if (op->d_wbf16) (void)hipFree(op->d_wbf16);
+  if (op->d_devop) (void)hipFree(op->d_devop);
   if (op->d_errors) (void)hipFree(op->d_errors);
   if (prev >= 0) (void)hipSetDevice(prev);
   op->d_stencil = nullptr;
   op->d_w64 = nullptr;
   op->d_w32 = nullptr;
   op->d_wbf16 = nullptr;
+  op->d_devop = nullptr;
   op->d_errors = nullptr;
   op->on_device = false;
 }
@@ -149,6 +151,11 @@ int upload(ft_operator* op) {
   d.w64 = op->d_w64;
   d.w32 = op->d_w32;
   d.wbf16 = op->d_wbf16;
+  if ((e = hipMalloc(&op->d_devop, sizeof(ft::DevOp))) != hipSuccess ||
+      (e = hipMemcpy(op->d_devop, &d, sizeof(ft::DevOp), hipMemcpyHostToDevice)) != hipSuccess) {
+    free_device(op);
+    return hip_fail(e, "uploading the operator view");
+  }
   return FT_OK;
 }
 
@@ -180,6 +187,8 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
 }
 
 }  // namespace
+
+void ft::set_last_error(const std::string& msg) { g_last_error = msg; }
 
 extern "C" {
 

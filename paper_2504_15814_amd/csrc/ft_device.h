@@ -1,0 +1,293 @@
+// Device bodies of the transfer: one (face, expansion anchor) work item per
+// wave.  Shared by the per-batch kernels and the fused plan kernel.
+//
+// apply_item: vector-ALU form (Section 2: the 1/9 segment of P or R per
+// hanging face, the same operator for every unknown; Section 4.2: vectorise
+// over the unknowns of the AoS halo).  The 64 lanes of the wave run over
+// unknowns, so every operator weight is wave-uniform: the weights stream
+// through the scalar cache into SGPRs and each loaded source value feeds R
+// fused multiply-adds held in VGPR accumulators.  Source loads and
+// destination stores are contiguous over the unknowns of a cell (AoS).  The
+// rotation / mirroring onto the reference face (Section 4.1) is not
+// materialised: the wave derives the physical strides of its face from the
+// orientation and walks the reference-frame stencil through them.
+//
+// mfma_item: float32 interpolation on the matrix cores.  Per anchor the
+// operator application is a small dense contraction Y (rows x unknowns) =
+// W (rows x stencil) . X (stencil x unknowns) (Section 6 suggests block
+// formats so that GEMM-type kernels apply), computed with
+// v_mfma_f32_32x32x16_bf16: M = the <= 27 fine rows of the anchor (padded to
+// 32), N = 32 unknowns per tile, K = 16 stencil points per step.  Float32 data
+// and the operator are split into bfloat16 parts (x = x0 + x1 + x2 exactly,
+// W = W0 + W1 + W2) and W0x0 + W0x1 + W1x0 (3 terms) or also W0x2 + W1x1 +
+// W2x0 (6 terms, compensating the split residuals) are accumulated in
+// float32.  The exact-copy row is written from the source value itself.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ft_internal.h"
+
+namespace ft {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// DIR 0: interpolation (src = coarse, dst = fine).  DIR 1: restriction
+// (src = fine, dst = coarse).  R rows per anchor; EC anchors per axis (0 = read
+// from the operator); COPY is the exact-copy row (its source is stencil entry
+// 0 of every block) or -1.  T storage, A accumulator, W weight type.
+template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W>
+__device__ __forceinline__ void apply_item(
+    const DevOp* __restrict__ op, const int face, const int e,
+    const int8_t* __restrict__ orientation, const int8_t* __restrict__ subface,
+    const int64_t* __restrict__ src_offset, const int64_t* __restrict__ dst_offset, const int U,
+    const T* __restrict__ src, const int64_t src_elems, T* __restrict__ dst,
+    const int64_t dst_elems, const W* __restrict__ weights, int* __restrict__ errors) {
+  constexpr int kGroup = 4;  // stencil loads in flight per wave before their FMAs
+  const int lane = threadIdx.x & 63;
+  const int E = EC > 0 ? EC : op->E;
+  const int eb = e % E, ec = e / E;
+  const int p = op->p, k = op->k;
+
+  const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
+  const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
+  const int64_t face_elems = (int64_t)(2 * k * p * p) * U;
+  const int64_t so = src_offset[face];
+  const int64_t dof = dst_offset[face];
+  const bool bad = o < 0 || o > 5 || s < 0 || s > 8 || so < 0 || dof < 0 ||
+                   so > src_elems - face_elems || dof > dst_elems - face_elems;
+  if (bad) {
+    if (e == 0 && lane == 0) atomicAdd(errors, 1);
+    return;
+  }
+  const FaceStrides st = face_strides(o % 3, p, k);
+  int nbase, nsign;
+  normal_map(DIR, o, k, &nbase, &nsign);
+  const int sb = s % 3, sc = s / 3;
+
+  // Anchor column in the source buffer and the block that serves it.
+  const int anc_b = DIR == 0 ? sb * E + eb : 3 * eb + 1;
+  const int anc_c = DIR == 0 ? sc * E + ec : 3 * ec + 1;
+  const int cls = axis_class(anc_b, p) * kAxisClasses + axis_class(anc_c, p);
+  const int width = op->width[cls];
+  const int start = op->start[cls];
+  const int anchor_cell = anc_b * st.sb + anc_c * st.sc + nbase * st.sa;
+  const int nstride = nsign * st.sa;
+  // First destination cell of this anchor and the strides of its rows.
+  const int dst_b = DIR == 0 ? 3 * eb : sb * E + eb;
+  const int dst_c = DIR == 0 ? 3 * ec : sc * E + ec;
+  const int dst_cell0 = nbase * st.sa + dst_b * st.sb + dst_c * st.sc;
+
+  const T* __restrict__ sp = src + so;
+  T* __restrict__ dp = dst + dof;
+  const int* __restrict__ pts = op->stencil + start;
+  const W* __restrict__ wts = weights + (int64_t)start * R;
+
+  for (int u0 = 0; u0 < U; u0 += 64) {
+    const int u = u0 + lane;
+    const bool act = u < U;
+    const int uu = act ? u : U - 1;  // idle lanes re-read a valid element
+    A acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = A(0);
+    A copy_val = A(0);
+    int q = 0;
+    for (; q + kGroup <= width; q += kGroup) {
+      A x[kGroup];
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) {
+        int n, db, dc;
+        unpack_point(pts[q + j], &n, &db, &dc);
+        const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+        x[j] = A(sp[(int64_t)cell * U + uu]);
+      }
+      if (COPY >= 0 && q == 0) copy_val = x[0];
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) {
+        const W* __restrict__ w = wts + (q + j) * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (r != COPY) acc[r] = fma(A(w[r]), x[j], acc[r]);
+      }
+    }
+    for (; q < width; ++q) {
+      int n, db, dc;
+      unpack_point(pts[q], &n, &db, &dc);
+      const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+      const A x = A(sp[(int64_t)cell * U + uu]);
+      if (COPY >= 0 && q == 0) copy_val = x;
+      const W* __restrict__ w = wts + q * R;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r != COPY) acc[r] = fma(A(w[r]), x, acc[r]);
+    }
+    if (!act) continue;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int dcell;
+      if (DIR == 0) {
+        const int g = r / 9, tb = (r / 3) % 3, tc = r % 3;
+        dcell = dst_cell0 + g * nstride + tb * st.sb + tc * st.sc;
+      } else {
+        dcell = dst_cell0 + r * nstride;
+      }
+      // Streaming (non-temporal) stores: the written halo is not re-read by
+      // this launch, and keeping it out of L2 preserves the source
+      // footprints that neighbouring anchors of the same face re-read.
+      __builtin_nontemporal_store(T(r == COPY ? copy_val : acc[r]), &dp[(int64_t)dcell * U + u]);
+    }
+  }
+}
+
+// Float32 interpolation on the matrix cores (see the file comment).
+// tile_all: the block's LDS transpose tiles, one per wave (wave_slot < 4).
+template <int R, int EC, int TERMS>
+__device__ __forceinline__ void mfma_item(
+    const DevOp* __restrict__ op, const int face, const int e, const int wave_slot,
+    float (*tile_all)[32][65], const int8_t* __restrict__ orientation,
+    const int8_t* __restrict__ subface, const int64_t* __restrict__ src_offset,
+    const int64_t* __restrict__ dst_offset, const int U, const float* __restrict__ src,
+    const int64_t src_elems, float* __restrict__ dst, const int64_t dst_elems,
+    int* __restrict__ errors) {
+  constexpr int COPY = 13;  // (g, tb, tc) = (1, 1, 1): the coarse centre itself
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, col = lane & 31;
+  const int E = EC > 0 ? EC : op->E;
+  const int eb = e % E, ec = e / E;
+  const int p = op->p, k = op->k;
+
+  const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
+  const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
+  const int64_t face_elems = (int64_t)(2 * k * p * p) * U;
+  const int64_t so = src_offset[face];
+  const int64_t dof = dst_offset[face];
+  const bool bad = o < 0 || o > 5 || s < 0 || s > 8 || so < 0 || dof < 0 ||
+                   so > src_elems - face_elems || dof > dst_elems - face_elems;
+  if (bad) {
+    if (e == 0 && lane == 0) atomicAdd(errors, 1);
+    return;
+  }
+  const FaceStrides st = face_strides(o % 3, p, k);
+  int nbase, nsign;
+  normal_map(0, o, k, &nbase, &nsign);
+  const int nstride = nsign * st.sa;
+  const int sb = s % 3, sc = s / 3;
+  const int anc_b = sb * E + eb, anc_c = sc * E + ec;
+  const int cls = axis_class(anc_b, p) * kAxisClasses + axis_class(anc_c, p);
+  const int width = op->width[cls];
+  const int start = op->start[cls];
+  const int nsteps = (width + kMfmaK - 1) / kMfmaK;
+  const int anchor_cell = anc_b * st.sb + anc_c * st.sc + nbase * st.sa;
+  const int dst_cell0 = nbase * st.sa + 3 * eb * st.sb + 3 * ec * st.sc;
+
+  const bf16x8* __restrict__ wt = reinterpret_cast<const bf16x8*>(op->wbf16);
+  const int* __restrict__ pts = op->stencil + start;
+  int copy_cell;
+  {
+    int n, db, dc;
+    unpack_point(pts[0], &n, &db, &dc);  // the copy source is entry 0
+    copy_cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+  }
+
+  const float* __restrict__ sp = src + so;
+  float* __restrict__ dp = dst + dof;
+  // Per-wave LDS tile for transposing the accumulators: rows x 64 unknowns
+  // (+1 pad); stores then write whole cells with lanes over unknowns.
+  float(*tile)[65] = tile_all[wave_slot];
+  for (int u0 = 0; u0 < U; u0 += 64) {
+    // Lanes run over 64 unknowns: every stencil cell is one coalesced load.
+    // The B operands of the two 32-unknown tiles are then formed in
+    // registers: for a k-step (16 stencil points) each lane packs its 8 + 8
+    // bfloat16 values, and v_permlane32_swap exchanges the upper half-wave of
+    // the first 8 with the lower half-wave of the second 8, which yields
+    // B[8h + i][col] for unknowns u0 + col (tile 0) and u0 + 32 + col
+    // (tile 1).
+    const int uu = min(u0 + lane, U - 1);
+    f32x16 acc0 = {}, acc1 = {};
+    for (int st_i = 0; st_i < nsteps; ++st_i) {
+      const bf16x8 w0 = wt[mfma_a_index(cls, st_i, 0, lane) / 8];
+      const bf16x8 w1 = wt[mfma_a_index(cls, st_i, 1, lane) / 8];
+      bf16x8 w2;
+      if (TERMS == 6) w2 = wt[mfma_a_index(cls, st_i, 2, lane) / 8];
+      float x[kMfmaK];
+#pragma unroll
+      for (int j = 0; j < kMfmaK; ++j) {
+        const int q = kMfmaK * st_i + j;
+        x[j] = 0.0f;
+        if (q < width) {
+          int n, db, dc;
+          unpack_point(pts[q], &n, &db, &dc);
+          const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+          x[j] = sp[(int64_t)cell * U + uu];
+        }
+      }
+      // Split x = x0 + x1 + x2 (bfloat16 parts), packed per 8 stencil points.
+      bf16x8 p0[2], p1[2], p2[2];
+#pragma unroll
+      for (int j = 0; j < kMfmaK; ++j) {
+        const __bf16 a0 = (__bf16)x[j];
+        const float r1 = x[j] - (float)a0;
+        const __bf16 a1 = (__bf16)r1;
+        p0[j / 8][j % 8] = a0;
+        p1[j / 8][j % 8] = a1;
+        if (TERMS == 6) p2[j / 8][j % 8] = (__bf16)(r1 - (float)a1);
+      }
+      auto to_tiles = [](bf16x8 lo, bf16x8 hi, bf16x8* t0, bf16x8* t1) {
+        u32x4 a = __builtin_bit_cast(u32x4, lo), b = __builtin_bit_cast(u32x4, hi);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const auto sw = __builtin_amdgcn_permlane32_swap(a[r], b[r], false, false);
+          a[r] = sw[0];
+          b[r] = sw[1];
+        }
+        *t0 = __builtin_bit_cast(bf16x8, a);
+        *t1 = __builtin_bit_cast(bf16x8, b);
+      };
+      bf16x8 b0a, b0b, b1a, b1b, b2a, b2b;
+      to_tiles(p0[0], p0[1], &b0a, &b0b);
+      to_tiles(p1[0], p1[1], &b1a, &b1b);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b0a, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b0b, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b1a, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b1b, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b0a, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b0b, acc1, 0, 0, 0);
+      if (TERMS == 6) {
+        to_tiles(p2[0], p2[1], &b2a, &b2b);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b2a, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b2b, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b1a, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b1b, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2, b0a, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2, b0b, acc1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int m = 8 * (v / 4) + 4 * h + (v % 4);
+      tile[m][col] = acc0[v];
+      tile[m][32 + col] = acc1[v];
+    }
+    // The tile is private to this wave: order its LDS writes before the reads.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int u = u0 + lane;
+    if (u < U) {
+      const float xc = sp[(int64_t)copy_cell * U + u];
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int g = m / 9, tb = (m / 3) % 3, tc = m % 3;
+        const int dcell = dst_cell0 + g * nstride + tb * st.sb + tc * st.sc;
+        __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+}  // namespace ft

@@ -122,10 +122,14 @@ struct ft_operator {
   float* d_w32 = nullptr;
   uint16_t* d_wbf16 = nullptr;
   int* d_errors = nullptr;
+  ft::DevOp* d_devop = nullptr;  // device copy of `dev` (kernels read it through a pointer)
   ft::DevOp dev{};
 };
 
 namespace ft {
+// Message returned by transfer_last_error() on the calling thread.
+void set_last_error(const std::string& msg);
+
 // Builder (host): fills blocks[] of op for op->direction/scheme/p/k.
 // Returns an empty string on success, else a message.
 std::string build_tables(ft_operator* op);

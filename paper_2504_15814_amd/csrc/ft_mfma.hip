@@ -1,180 +1,32 @@
-// Interpolation on the matrix cores for float32 face data (the mixed form).
-//
-// Per (face, anchor) the operator application is a small dense contraction
-// Y (rows x unknowns) = W (rows x stencil) . X (stencil x unknowns) (Section 2:
-// the same operator for every unknown; Section 6 suggests block formats so
-// that GEMM-type kernels apply).  One wave computes it with
-// v_mfma_f32_32x32x16_bf16: M = the <= 27 fine rows of the anchor (padded to
-// 32), N = 32 unknowns per tile, K = 16 stencil points per step.  Float32 data
-// and the operator are split into bfloat16 parts (x = x0 + x1 + x2 exactly,
-// W = W0 + W1 + W2) and the products W0x0 + W0x1 + W1x0 (3 terms) or also
-// W0x2 + W1x1 + W2x0 (6 terms, compensating the split residuals) are
-// accumulated in float32.  The exact-copy row is written from the source
-// value itself.
+// Float32 interpolation on the matrix cores for one operator and a batch of
+// hanging faces (split-bfloat16 MFMA; the per-item work is mfma_item in
+// ft_device.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "ft_device.h"
 #include "ft_internal.h"
 #include "ft_kernels.h"
 
 namespace ft {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 template <int R, int EC, int TERMS>
 __global__ __launch_bounds__(256) void interp_mfma_kernel(
-    const DevOp op, const int64_t n_faces, const int waves_per_block,
+    const DevOp* __restrict__ op, const int64_t n_faces, const int waves_per_block,
     const int8_t* __restrict__ orientation, const int8_t* __restrict__ subface,
     const int64_t* __restrict__ src_offset, const int64_t* __restrict__ dst_offset, const int U,
     const float* __restrict__ src, const int64_t src_elems, float* __restrict__ dst,
     const int64_t dst_elems, int* __restrict__ errors) {
-  constexpr int COPY = 13;  // (g, tb, tc) = (1, 1, 1): the coarse centre itself
+  __shared__ float tile_all[4][32][65];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int h = lane >> 5, col = lane & 31;
-  const int E = EC > 0 ? EC : op.E;
+  const int E = EC > 0 ? EC : op->E;
   const int anchors = E * E;
   const int item = (int)blockIdx.x * waves_per_block + wave;
   const int face = item / anchors;
   if (face >= n_faces) return;
-  const int e = item - face * anchors;
-  const int eb = e % E, ec = e / E;
-  const int p = op.p, k = op.k;
-
-  const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
-  const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
-  const int64_t face_elems = (int64_t)(2 * k * p * p) * U;
-  const int64_t so = src_offset[face];
-  const int64_t dof = dst_offset[face];
-  const bool bad = o < 0 || o > 5 || s < 0 || s > 8 || so < 0 || dof < 0 ||
-                   so > src_elems - face_elems || dof > dst_elems - face_elems;
-  if (bad) {
-    if (e == 0 && lane == 0) atomicAdd(errors, 1);
-    return;
-  }
-  const FaceStrides st = face_strides(o % 3, p, k);
-  int nbase, nsign;
-  normal_map(0, o, k, &nbase, &nsign);
-  const int nstride = nsign * st.sa;
-  const int sb = s % 3, sc = s / 3;
-  const int anc_b = sb * E + eb, anc_c = sc * E + ec;
-  const int cls = axis_class(anc_b, p) * kAxisClasses + axis_class(anc_c, p);
-  const int width = op.width[cls];
-  const int start = op.start[cls];
-  const int nsteps = (width + kMfmaK - 1) / kMfmaK;
-  const int anchor_cell = anc_b * st.sb + anc_c * st.sc + nbase * st.sa;
-  const int dst_cell0 = nbase * st.sa + 3 * eb * st.sb + 3 * ec * st.sc;
-
-  const bf16x8* __restrict__ wt = reinterpret_cast<const bf16x8*>(op.wbf16);
-  const int* __restrict__ pts = op.stencil + start;
-  int copy_cell;
-  {
-    int n, db, dc;
-    unpack_point(pts[0], &n, &db, &dc);  // the copy source is entry 0
-    copy_cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
-  }
-
-  const float* __restrict__ sp = src + so;
-  float* __restrict__ dp = dst + dof;
-  // Per-wave LDS tile for transposing the accumulators: rows x 64 unknowns
-  // (+1 pad); stores then write whole cells with lanes over unknowns.
-  __shared__ float tile_all[4][32][65];
-  float(*tile)[65] = tile_all[wave];
-  for (int u0 = 0; u0 < U; u0 += 64) {
-    // Lanes run over 64 unknowns: every stencil cell is one coalesced load.
-    // The B operands of the two 32-unknown tiles are then formed in
-    // registers: for a k-step (16 stencil points) each lane packs its 8 + 8
-    // bfloat16 values, and v_permlane32_swap exchanges the upper half-wave of
-    // the first 8 with the lower half-wave of the second 8, which yields
-    // B[8h + i][col] for unknowns u0 + col (tile 0) and u0 + 32 + col
-    // (tile 1).
-    const int uu = min(u0 + lane, U - 1);
-    f32x16 acc0 = {}, acc1 = {};
-    for (int st_i = 0; st_i < nsteps; ++st_i) {
-      const bf16x8 w0 = wt[mfma_a_index(cls, st_i, 0, lane) / 8];
-      const bf16x8 w1 = wt[mfma_a_index(cls, st_i, 1, lane) / 8];
-      bf16x8 w2;
-      if (TERMS == 6) w2 = wt[mfma_a_index(cls, st_i, 2, lane) / 8];
-      float x[kMfmaK];
-#pragma unroll
-      for (int j = 0; j < kMfmaK; ++j) {
-        const int q = kMfmaK * st_i + j;
-        x[j] = 0.0f;
-        if (q < width) {
-          int n, db, dc;
-          unpack_point(pts[q], &n, &db, &dc);
-          const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
-          x[j] = sp[(int64_t)cell * U + uu];
-        }
-      }
-      // Split x = x0 + x1 + x2 (bfloat16 parts), packed per 8 stencil points.
-      bf16x8 p0[2], p1[2], p2[2];
-#pragma unroll
-      for (int j = 0; j < kMfmaK; ++j) {
-        const __bf16 a0 = (__bf16)x[j];
-        const float r1 = x[j] - (float)a0;
-        const __bf16 a1 = (__bf16)r1;
-        p0[j / 8][j % 8] = a0;
-        p1[j / 8][j % 8] = a1;
-        if (TERMS == 6) p2[j / 8][j % 8] = (__bf16)(r1 - (float)a1);
-      }
-      auto to_tiles = [](bf16x8 lo, bf16x8 hi, bf16x8* t0, bf16x8* t1) {
-        u32x4 a = __builtin_bit_cast(u32x4, lo), b = __builtin_bit_cast(u32x4, hi);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const auto sw = __builtin_amdgcn_permlane32_swap(a[r], b[r], false, false);
-          a[r] = sw[0];
-          b[r] = sw[1];
-        }
-        *t0 = __builtin_bit_cast(bf16x8, a);
-        *t1 = __builtin_bit_cast(bf16x8, b);
-      };
-      bf16x8 b0a, b0b, b1a, b1b, b2a, b2b;
-      to_tiles(p0[0], p0[1], &b0a, &b0b);
-      to_tiles(p1[0], p1[1], &b1a, &b1b);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b0a, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b0b, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b1a, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b1b, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b0a, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b0b, acc1, 0, 0, 0);
-      if (TERMS == 6) {
-        to_tiles(p2[0], p2[1], &b2a, &b2b);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b2a, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, b2b, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b1a, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b1b, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2, b0a, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2, b0b, acc1, 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int m = 8 * (v / 4) + 4 * h + (v % 4);
-      tile[m][col] = acc0[v];
-      tile[m][32 + col] = acc1[v];
-    }
-    // The tile is private to this wave: order its LDS writes before the reads.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int u = u0 + lane;
-    if (u < U) {
-      const float xc = sp[(int64_t)copy_cell * U + u];
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int g = m / 9, tb = (m / 3) % 3, tc = m % 3;
-        const int dcell = dst_cell0 + g * nstride + tb * st.sb + tc * st.sc;
-        __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
+  mfma_item<R, EC, TERMS>(op, face, item - face * anchors, wave, tile_all, orientation, subface,
+                          src_offset, dst_offset, U, src, src_elems, dst, dst_elems, errors);
 }
 
 template <int R, int EC, int TERMS>
@@ -186,7 +38,7 @@ static hipError_t launch_mfma_one(const ft_operator* op, const LaunchArgs& la,
     const int64_t nf = std::min<int64_t>(chunk, la.n_faces - f0);
     const int64_t blocks = (nf * anchors + cfg.waves_per_block - 1) / cfg.waves_per_block;
     hipLaunchKernelGGL((interp_mfma_kernel<R, EC, TERMS>), dim3((unsigned)blocks),
-                       dim3(64 * cfg.waves_per_block), 0, stream, op->dev, nf,
+                       dim3(64 * cfg.waves_per_block), 0, stream, op->d_devop, nf,
                        cfg.waves_per_block, la.orientation + f0, la.subface + f0,
                        la.src_offset + f0, la.dst_offset + f0, la.U,
                        static_cast<const float*>(la.src), la.src_elems,

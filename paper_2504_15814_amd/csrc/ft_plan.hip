@@ -1,0 +1,454 @@
+// Plans: uneven mixes of hanging faces (orientation, direction, scheme, patch
+// size, halo depth) in one persistent launch, an autotuner over launch
+// shapes, and HIP-graph capture of whole steps.
+//
+// Device side: a plan phase is a table of segments, one per batch, each a
+// contiguous range of (face, anchor) work items.  A fixed grid of waves walks
+// the items with a grid stride; since a wave's items only increase, it
+// advances its segment cursor linearly (amortised O(1) per item) and
+// dispatches to the same per-item bodies as the per-batch kernels
+// (ft_device.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "facetransfer.h"
+#include "ft_device.h"
+#include "ft_internal.h"
+#include "ft_kernels.h"
+
+namespace ft {
+
+enum PlanKind { kInterp18, kInterp27, kRestrict2Inject, kRestrict2Plain, kRestrict3Inject, kRestrict3Plain };
+
+struct PlanSeg {
+  const DevOp* op;
+  const int8_t* orientation;
+  const int8_t* subface;
+  const int64_t* coarse_offset;
+  const int64_t* fine_offset;
+  int* errors;
+  int64_t item0;     // first work item of the segment
+  int64_t item_end;  // one past its last work item
+  int kind;
+  int anchors;
+};
+
+// MODE 0: interpolation on the vector ALUs in precision T; MODE 3 / 6:
+// float32 interpolation on the matrix cores with that many bfloat16 product
+// terms.  Restriction always sums in float64.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ segs,
+                                                   const int64_t total, const int wpb,
+                                                   const int remap, const int U,
+                                                   T* __restrict__ coarse, const int64_t coarse_elems,
+                                                   T* __restrict__ fine, const int64_t fine_elems) {
+  __shared__ float tile_all[MODE ? 4 : 1][32][65];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t b = blockIdx.x;
+  if (remap) {
+    // Block i runs on XCD i % 8: give every XCD a contiguous range of
+    // logical waves, so that neighbouring items share an L2.
+    const int64_t nb = gridDim.x, per = nb / 8, full = per * 8;
+    if (b < full) b = (b % 8) * per + b / 8;
+  }
+  const int64_t stride = (int64_t)gridDim.x * wpb;
+  int sg = 0;
+  for (int64_t it = b * wpb + wave; it < total; it += stride) {
+    while (it >= segs[sg].item_end) ++sg;
+    const PlanSeg* __restrict__ S = segs + sg;
+    const int anchors = S->anchors;
+    const int64_t local = it - S->item0;
+    const int face = (int)(local / anchors);
+    const int e = (int)(local - (int64_t)face * anchors);
+    const DevOp* __restrict__ op = S->op;
+    switch (S->kind) {
+      case kInterp18:
+        if constexpr (MODE == 0)
+          apply_item<0, 18, 0, 13, T, T, T>(op, face, e, S->orientation, S->subface,
+                                            S->coarse_offset, S->fine_offset, U, coarse,
+                                            coarse_elems, fine, fine_elems,
+                                            (const T*)(sizeof(T) == 8 ? (const void*)op->w64
+                                                                      : (const void*)op->w32),
+                                            S->errors);
+        else
+          mfma_item<18, 0, MODE>(op, face, e, wave, tile_all, S->orientation, S->subface,
+                                 S->coarse_offset, S->fine_offset, U, (const float*)coarse,
+                                 coarse_elems, (float*)fine, fine_elems, S->errors);
+        break;
+      case kInterp27:
+        if constexpr (MODE == 0)
+          apply_item<0, 27, 0, 13, T, T, T>(op, face, e, S->orientation, S->subface,
+                                            S->coarse_offset, S->fine_offset, U, coarse,
+                                            coarse_elems, fine, fine_elems,
+                                            (const T*)(sizeof(T) == 8 ? (const void*)op->w64
+                                                                      : (const void*)op->w32),
+                                            S->errors);
+        else
+          mfma_item<27, 0, MODE>(op, face, e, wave, tile_all, S->orientation, S->subface,
+                                 S->coarse_offset, S->fine_offset, U, (const float*)coarse,
+                                 coarse_elems, (float*)fine, fine_elems, S->errors);
+        break;
+      case kRestrict2Inject:
+        apply_item<1, 2, 0, 0, T, double, double>(op, face, e, S->orientation, S->subface,
+                                                  S->fine_offset, S->coarse_offset, U, fine,
+                                                  fine_elems, coarse, coarse_elems, op->w64,
+                                                  S->errors);
+        break;
+      case kRestrict2Plain:
+        apply_item<1, 2, 0, -1, T, double, double>(op, face, e, S->orientation, S->subface,
+                                                   S->fine_offset, S->coarse_offset, U, fine,
+                                                   fine_elems, coarse, coarse_elems, op->w64,
+                                                   S->errors);
+        break;
+      case kRestrict3Inject:
+        apply_item<1, 3, 0, 0, T, double, double>(op, face, e, S->orientation, S->subface,
+                                                  S->fine_offset, S->coarse_offset, U, fine,
+                                                  fine_elems, coarse, coarse_elems, op->w64,
+                                                  S->errors);
+        break;
+      default:
+        apply_item<1, 3, 0, -1, T, double, double>(op, face, e, S->orientation, S->subface,
+                                                   S->fine_offset, S->coarse_offset, U, fine,
+                                                   fine_elems, coarse, coarse_elems, op->w64,
+                                                   S->errors);
+        break;
+    }
+  }
+}
+
+}  // namespace ft
+
+struct ft_plan {
+  std::vector<ft_plan_batch> batches;
+  int U = 0, dtype = 0, flags = 0, device = -1, n_cu = 256;
+  void* coarse = nullptr;
+  void* fine = nullptr;
+  int64_t coarse_elems = 0, fine_elems = 0;
+  int64_t schedule = 0;
+  ft::PlanSeg* d_segs[2] = {nullptr, nullptr};
+  int nseg[2] = {0, 0};
+  int64_t total[2] = {0, 0};
+};
+
+struct ft_graph {
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
+};
+
+namespace {
+
+int pfail(int code, const std::string& msg) {
+  ft::set_last_error(msg);
+  return code;
+}
+
+int phip(hipError_t e, const char* what) {
+  return pfail(FT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int wpb_of(int64_t s) { return (int)(s & 0xff); }
+int bpc_of(int64_t s) { return (int)((s >> 8) & 0xff); }
+int remap_of(int64_t s) { return (int)((s >> 16) & 1); }
+int heavy_of(int64_t s) { return (int)((s >> 17) & 1); }
+
+int plan_kind(const ft_operator* op) {
+  if (op->direction == FT_INTERPOLATE) return op->k == 2 ? ft::kInterp18 : ft::kInterp27;
+  const bool inject = op->copy_row == 0;
+  if (op->k == 2) return inject ? ft::kRestrict2Inject : ft::kRestrict2Plain;
+  return inject ? ft::kRestrict3Inject : ft::kRestrict3Plain;
+}
+
+// Relative cost of one work item (rows x widest block), for heavy-first order.
+double item_cost(const ft_operator* op) {
+  int w = 0;
+  for (int c = 0; c < ft::kClasses; ++c) w = std::max(w, op->blocks[c].width);
+  return (double)op->R * w + 64.0 * op->R;  // FMAs + stores
+}
+
+void free_tables(ft_plan* plan) {
+  for (int ph = 0; ph < 2; ++ph) {
+    if (plan->d_segs[ph]) (void)hipFree(plan->d_segs[ph]);
+    plan->d_segs[ph] = nullptr;
+    plan->nseg[ph] = 0;
+    plan->total[ph] = 0;
+  }
+}
+
+// (Re)build the device segment tables for the current schedule.
+int upload_tables(ft_plan* plan) {
+  free_tables(plan);
+  const bool phased = plan->flags & FT_PLAN_RESTRICT_FIRST;
+  for (int ph = 0; ph < 2; ++ph) {
+    std::vector<int> idx;
+    for (int i = 0; i < (int)plan->batches.size(); ++i) {
+      const ft_plan_batch& b = plan->batches[i];
+      if (b.n_faces == 0) continue;
+      const int phase = phased ? (b.op->direction == FT_RESTRICT ? 0 : 1) : 0;
+      if (phase == ph) idx.push_back(i);
+    }
+    if (heavy_of(plan->schedule))
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+        return item_cost(plan->batches[a].op) > item_cost(plan->batches[c].op);
+      });
+    std::vector<ft::PlanSeg> segs;
+    int64_t item = 0;
+    for (int i : idx) {
+      const ft_plan_batch& b = plan->batches[i];
+      ft::PlanSeg sgm;
+      sgm.op = b.op->d_devop;
+      sgm.orientation = b.orientation;
+      sgm.subface = b.subface;
+      sgm.coarse_offset = b.coarse_offset;
+      sgm.fine_offset = b.fine_offset;
+      sgm.errors = b.op->d_errors;
+      sgm.anchors = b.op->E * b.op->E;
+      sgm.kind = plan_kind(b.op);
+      sgm.item0 = item;
+      item += b.n_faces * sgm.anchors;
+      sgm.item_end = item;
+      segs.push_back(sgm);
+    }
+    if (segs.empty()) continue;
+    hipError_t e = hipMalloc(&plan->d_segs[ph], segs.size() * sizeof(ft::PlanSeg));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? pfail(FT_ERR_NOMEM, "plan table")
+                                                         : phip(e, "hipMalloc plan table");
+    e = hipMemcpy(plan->d_segs[ph], segs.data(), segs.size() * sizeof(ft::PlanSeg),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return phip(e, "uploading the plan table");
+    plan->nseg[ph] = (int)segs.size();
+    plan->total[ph] = item;
+  }
+  return FT_OK;
+}
+
+template <typename T, int MODE>
+hipError_t launch_phase(const ft_plan* plan, int ph, hipStream_t stream) {
+  const int wpb = wpb_of(plan->schedule);
+  const int64_t want = (plan->total[ph] + wpb - 1) / wpb;
+  const int64_t blocks = std::min<int64_t>(want, (int64_t)plan->n_cu * bpc_of(plan->schedule));
+  hipLaunchKernelGGL((ft::plan_kernel<T, MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0, stream,
+                     plan->d_segs[ph], plan->total[ph], wpb, remap_of(plan->schedule), plan->U,
+                     static_cast<T*>(plan->coarse), plan->coarse_elems,
+                     static_cast<T*>(plan->fine), plan->fine_elems);
+  return hipGetLastError();
+}
+
+int run_plan(const ft_plan* plan, hipStream_t stream) {
+  for (int ph = 0; ph < 2; ++ph) {
+    if (plan->total[ph] == 0) continue;
+    hipError_t e;
+    switch (plan->dtype) {
+      case FT_F64: e = launch_phase<double, 0>(plan, ph, stream); break;
+      case FT_F32: e = launch_phase<float, 0>(plan, ph, stream); break;
+      case FT_F32_BF16X3: e = launch_phase<float, 3>(plan, ph, stream); break;
+      default: e = launch_phase<float, 6>(plan, ph, stream); break;
+    }
+    if (e != hipSuccess) return phip(e, "run_transfer_plan launch");
+  }
+  return FT_OK;
+}
+
+bool valid_schedule(int64_t s) {
+  const int w = wpb_of(s), b = bpc_of(s);
+  return (w == 1 || w == 2 || w == 4) && b >= 1 && b <= 64 && (s >> 18) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknowns, int dtype,
+                        void* coarse, int64_t coarse_elems, void* fine, int64_t fine_elems,
+                        int flags, ft_plan** out) {
+  if (!out) return pfail(FT_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!batches || n_batches < 1) return pfail(FT_ERR_INVALID, "need at least one batch");
+  if (unknowns < 1 || unknowns > 4096) return pfail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
+  if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return pfail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (flags & ~FT_PLAN_RESTRICT_FIRST) return pfail(FT_ERR_INVALID, "unknown flags");
+  if (!coarse || !fine || coarse_elems < 0 || fine_elems < 0 || coarse == fine)
+    return pfail(FT_ERR_INVALID, "bad coarse / fine buffers");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return phip(e, "hipGetDevice");
+  for (int i = 0; i < n_batches; ++i) {
+    const ft_plan_batch& b = batches[i];
+    if (!b.op || b.n_faces < 0) return pfail(FT_ERR_INVALID, "batch with NULL op or n_faces < 0");
+    if (!b.op->on_device || b.op->device != dev)
+      return pfail(FT_ERR_INVALID, "batch operator is host-only or on another device");
+    if (b.n_faces > 0 && (!b.orientation || !b.subface || !b.coarse_offset || !b.fine_offset))
+      return pfail(FT_ERR_INVALID, "batch with NULL descriptor arrays");
+    if (b.n_faces * (int64_t)b.op->E * b.op->E > ((int64_t)1 << 40))
+      return pfail(FT_ERR_UNSUPPORTED, "batch too large");
+    if (dtype >= FT_F32_BF16X3 && b.op->direction == FT_INTERPOLATE && !b.op->d_wbf16)
+      return pfail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
+  }
+  ft_plan* plan = new (std::nothrow) ft_plan();
+  if (!plan) return pfail(FT_ERR_NOMEM, "host allocation failed");
+  plan->batches.assign(batches, batches + n_batches);
+  plan->U = unknowns;
+  plan->dtype = dtype;
+  plan->flags = flags;
+  plan->device = dev;
+  plan->coarse = coarse;
+  plan->fine = fine;
+  plan->coarse_elems = coarse_elems;
+  plan->fine_elems = fine_elems;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    plan->n_cu = ncu;
+  plan->schedule = 4 | (8 << 8);  // 4 waves per block, 8 blocks per CU
+  const int rc = upload_tables(plan);
+  if (rc != FT_OK) {
+    free_tables(plan);
+    delete plan;
+    return rc;
+  }
+  *out = plan;
+  ft::set_last_error("");
+  return FT_OK;
+}
+
+int run_transfer_plan(const ft_plan* plan, void* stream) {
+  if (!plan) return pfail(FT_ERR_INVALID, "plan is NULL");
+  const int rc = run_plan(plan, (hipStream_t)stream);
+  if (rc == FT_OK) ft::set_last_error("");
+  return rc;
+}
+
+int transfer_plan_set_schedule(ft_plan* plan, int64_t schedule) {
+  if (!plan) return pfail(FT_ERR_INVALID, "plan is NULL");
+  if (!valid_schedule(schedule)) return pfail(FT_ERR_INVALID, "invalid schedule");
+  const bool reorder = heavy_of(schedule) != heavy_of(plan->schedule);
+  plan->schedule = schedule;
+  if (reorder) return upload_tables(plan);
+  return FT_OK;
+}
+
+int transfer_plan_get_schedule(const ft_plan* plan, int64_t* schedule) {
+  if (!plan || !schedule) return pfail(FT_ERR_INVALID, "NULL plan or schedule");
+  *schedule = plan->schedule;
+  return FT_OK;
+}
+
+int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_schedule,
+                           double* best_ms) {
+  if (!plan || reps < 1) return pfail(FT_ERR_INVALID, "NULL plan or reps < 1");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return pfail(FT_ERR_HIP, "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return pfail(FT_ERR_HIP, "hipEventCreate");
+  }
+  const int64_t orig = plan->schedule;
+  int64_t best = orig;
+  double best_t = INFINITY;
+  int rc = FT_OK;
+  for (int heavy = 0; heavy < 2 && rc == FT_OK; ++heavy)
+    for (int remap = 0; remap < 2 && rc == FT_OK; ++remap)
+      for (int wpb : {2, 4})
+        for (int bpc : {2, 4, 8, 16}) {
+          const int64_t sch = wpb | ((int64_t)bpc << 8) | ((int64_t)remap << 16) |
+                              ((int64_t)heavy << 17);
+          if ((rc = transfer_plan_set_schedule(plan, sch)) != FT_OK) break;
+          if ((rc = run_plan(plan, s)) != FT_OK) break;  // warm-up
+          (void)hipEventRecord(e0, s);
+          for (int r = 0; r < reps && rc == FT_OK; ++r) rc = run_plan(plan, s);
+          (void)hipEventRecord(e1, s);
+          if (rc != FT_OK) break;
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = pfail(FT_ERR_HIP, "autotune synchronisation");
+            break;
+          }
+          float ms = 0.0f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          const double t = ms / reps;
+          if (t < best_t) {
+            best_t = t;
+            best = sch;
+          }
+        }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != FT_OK) {
+    (void)transfer_plan_set_schedule(plan, orig);
+    return rc;
+  }
+  rc = transfer_plan_set_schedule(plan, best);
+  if (rc != FT_OK) return rc;
+  if (best_schedule) *best_schedule = best;
+  if (best_ms) *best_ms = best_t;
+  ft::set_last_error("");
+  return FT_OK;
+}
+
+int destroy_transfer_plan(ft_plan* plan) {
+  if (!plan) return FT_OK;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(plan->device);
+  free_tables(plan);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  delete plan;
+  return FT_OK;
+}
+
+int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out) {
+  if (!out) return pfail(FT_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!plan || steps < 1) return pfail(FT_ERR_INVALID, "NULL plan or steps < 1");
+  ft_graph* g = new (std::nothrow) ft_graph();
+  if (!g) return pfail(FT_ERR_NOMEM, "host allocation failed");
+  g->device = plan->device;
+  hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return phip(e, "hipStreamCreateWithFlags");
+  }
+  int rc = FT_OK;
+  e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) rc = phip(e, "hipStreamBeginCapture");
+  for (int i = 0; i < steps && rc == FT_OK; ++i) rc = run_plan(plan, g->stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(g->stream, &graph);
+  if (rc == FT_OK && e != hipSuccess) rc = phip(e, "hipStreamEndCapture");
+  g->graph = graph;
+  if (rc == FT_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = phip(e, "hipGraphInstantiate");
+  }
+  if (rc != FT_OK) {
+    destroy_transfer_graph(g);
+    return rc;
+  }
+  *out = g;
+  ft::set_last_error("");
+  return FT_OK;
+}
+
+int transfer_graph_launch(const ft_graph* graph, void* stream) {
+  if (!graph || !graph->exec) return pfail(FT_ERR_INVALID, "graph is NULL");
+  const hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return phip(e, "hipGraphLaunch");
+  ft::set_last_error("");
+  return FT_OK;
+}
+
+int destroy_transfer_graph(ft_graph* graph) {
+  if (!graph) return FT_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  if (graph->stream) (void)hipStreamDestroy(graph->stream);
+  delete graph;
+  return FT_OK;
+}
+
+}  // extern "C"

@@ -275,3 +275,94 @@ def sentinel_fill_(t, value=-7.25e11):
     """Fill a destination buffer with a recognisable value."""
     t.fill_(value)
     return t
+
+
+# ---------------------------------------------------------------------------
+# Workload 4: an uneven mix of hanging faces in shared pools
+# ---------------------------------------------------------------------------
+@dataclass
+class MixedBatch:
+    """Independent hanging faces of different (p, k, scheme, direction) whose
+    coarse and fine buffers live in two flat pools.  Face f owns
+    2 k_f p_f^2 U elements at coarse_offset[f] / fine_offset[f]."""
+
+    U: int
+    p: torch.Tensor  # int64 [n] (host)
+    k: torch.Tensor
+    scheme: torch.Tensor
+    direction: torch.Tensor  # 0 interpolate, 1 restrict
+    orientation: torch.Tensor  # int8 [n] (device)
+    subface: torch.Tensor
+    coarse_offset: torch.Tensor  # int64 [n] (device)
+    fine_offset: torch.Tensor
+    coarse: torch.Tensor
+    fine: torch.Tensor
+
+    @property
+    def n(self):
+        return int(self.p.numel())
+
+    def groups(self):
+        """{(direction, scheme, p, k): host index tensor of its faces}, faces
+        in their interleaved pool order."""
+        key = ((self.direction * 4 + self.scheme) * 64 + self.p) * 4 + self.k
+        out = {}
+        for kv in torch.unique(key).tolist():
+            idx = torch.nonzero(key == kv).flatten()
+            f = int(idx[0])
+            out[(int(self.direction[f]), int(self.scheme[f]), int(self.p[f]), int(self.k[f]))] = idx
+        return out
+
+    def subset(self, idx):
+        """Descriptor arrays (device) of the faces idx (host index tensor)."""
+        dev = self.orientation.device
+        i = idx.to(dev)
+        return (self.orientation[i].contiguous(), self.subface[i].contiguous(),
+                self.coarse_offset[i].contiguous(), self.fine_offset[i].contiguous())
+
+
+def workload4(n_faces=50000, device="cpu", dtype=torch.float32, U=59, seed=SEED_BASE + 4):
+    """50,000 faces: p in {6, 9, 12} at 30/50/20 %, k in {2, 3} uniform, scheme
+    in {d-linear, Taylor-2, Taylor-3} uniform, direction Bernoulli(1/2)
+    interleaved; bump fields with 1e-3 noise, U = 59."""
+    gen = torch.Generator().manual_seed(seed)
+    r = torch.rand(n_faces, generator=gen)
+    p = torch.where(r < 0.3, 6, torch.where(r < 0.8, 9, 12)).to(torch.int64)
+    k = torch.randint(2, 4, (n_faces,), generator=gen)
+    scheme = torch.randint(1, 4, (n_faces,), generator=gen)
+    direction = torch.randint(0, 2, (n_faces,), generator=gen)
+    orient = torch.randint(0, 6, (n_faces,), generator=gen)
+    sub = torch.randint(0, 9, (n_faces,), generator=gen)
+    origin = face_origins(gen, orient, 9)
+    fieldfn = bump_field(gen, U)
+    elems = 2 * k * p * p * U
+    offs = torch.cumsum(elems, 0) - elems
+    total = int(elems.sum())
+    mb = MixedBatch(U, p, k, scheme, direction, orient.to(torch.int8).to(device), sub.to(torch.int8).to(device),
+                    offs.to(device), offs.clone().to(device),
+                    torch.zeros(total, dtype=dtype, device=device), torch.zeros(total, dtype=dtype, device=device))
+    noise_seed = int(torch.randint(0, 2**62, (1,), generator=gen).item())
+    noise_gen = torch.Generator(device=device).manual_seed(noise_seed)
+    for pp in (6, 9, 12):
+        for kk in (2, 3):
+            sel = torch.nonzero((p == pp) & (k == kk)).flatten()
+            if sel.numel() == 0:
+                continue
+            E = 2 * kk * pp * pp * U
+            cc = {o: coarse_centres(o, pp, kk, device) for o in range(6)}
+            fc = {(o, s): fine_centres(o, pp, kk, s, device) for o in range(6) for s in range(9)}
+            ol, sl = orient[sel].tolist(), sub[sel].tolist()
+            for c0 in range(0, sel.numel(), 1024):
+                part = sel[c0:c0 + 1024]
+                idx = list(range(c0, c0 + part.numel()))
+                org = origin[part].to(device)[:, None, :]
+                pos_c = torch.stack([cc[ol[i]] for i in idx]) * H_FINE + org
+                pos_f = torch.stack([fc[(ol[i], sl[i])] for i in idx]) * H_FINE + org
+                vc = fieldfn(pos_c.reshape(-1, 3)).reshape(part.numel(), E)
+                vf = fieldfn(pos_f.reshape(-1, 3)).reshape(part.numel(), E)
+                vc += 1e-3 * torch.randn(vc.shape, generator=noise_gen, dtype=torch.float64, device=device)
+                vf += 1e-3 * torch.randn(vf.shape, generator=noise_gen, dtype=torch.float64, device=device)
+                where = (offs[part].to(device)[:, None] + torch.arange(E, device=device)[None, :]).reshape(-1)
+                mb.coarse[where] = vc.reshape(-1).to(dtype)
+                mb.fine[where] = vf.reshape(-1).to(dtype)
+    return mb

@@ -149,3 +149,30 @@ def test_apply_without_gpu_fails_cleanly():
     rc = lib.build_transfer_operator(0, 2, 9, 3, 0, ctypes.byref(h))
     assert rc == api.FT_ERR_HIP
     assert h.value is None
+
+
+def test_plan_checks_happen_on_host():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    p = ctypes.c_void_p(64)
+    assert lib.build_transfer_plan(None, 1, 59, 0, p, 100, ctypes.c_void_p(128), 100, 0, ctypes.byref(h)) == api.FT_ERR_INVALID
+    op = api.build_transfer_operator(0, 2, 9, 3, api.FT_BUILD_HOST_ONLY)
+    arr = (_lib.PlanBatch * 1)()
+    arr[0] = _lib.PlanBatch(op.handle, 1, 8, 8, 8, 8)
+    rc = lib.build_transfer_plan(arr, 1, 59, 0, p, 100, ctypes.c_void_p(128), 100, 0, ctypes.byref(h))
+    assert rc in (api.FT_ERR_INVALID, api.FT_ERR_HIP)  # host-only operator (or no device at all)
+    assert lib.build_transfer_plan(arr, 0, 59, 0, p, 100, ctypes.c_void_p(128), 100, 0, ctypes.byref(h)) == api.FT_ERR_INVALID
+    assert lib.build_transfer_plan(arr, 1, 0, 0, p, 100, ctypes.c_void_p(128), 100, 0, ctypes.byref(h)) == api.FT_ERR_UNSUPPORTED
+    assert lib.build_transfer_plan(arr, 1, 59, 9, p, 100, ctypes.c_void_p(128), 100, 0, ctypes.byref(h)) == api.FT_ERR_UNSUPPORTED
+    assert lib.build_transfer_plan(arr, 1, 59, 0, p, 100, p, 100, 0, ctypes.byref(h)) == api.FT_ERR_INVALID
+    assert lib.run_transfer_plan(None, None) == api.FT_ERR_INVALID
+    assert lib.transfer_plan_set_schedule(None, 4) == api.FT_ERR_INVALID
+    assert lib.transfer_plan_capture(None, 1, ctypes.byref(h)) == api.FT_ERR_INVALID
+    assert lib.transfer_graph_launch(None, None) == api.FT_ERR_INVALID
+    assert lib.destroy_transfer_plan(None) == api.FT_OK
+    assert lib.destroy_transfer_graph(None) == api.FT_OK
+
+
+def test_schedule_packing_roundtrip():
+    s = api.pack_schedule(2, 16, 1, 1)
+    assert api.unpack_schedule(s) == {"waves_per_block": 2, "blocks_per_cu": 16, "xcd_remap": 1, "heavy_first": 1}

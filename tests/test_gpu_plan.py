@@ -1,0 +1,189 @@
+"""Plans (one persistent launch over an uneven mix), schedules, the autotuner
+and HIP-graph capture, all through the C ABI.
+
+A plan runs the same per-item code as the per-batch kernels, so its output
+must equal the per-batch calls bit for bit under every schedule; graph
+replays must equal eager runs bit for bit.  A sample is also checked against
+the FP64 oracle.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_15814_amd import api
+from paper_2504_15814_amd import workloads as wl
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gh.require_gpu()
+
+
+@pytest.fixture(scope="module")
+def mixed32(dev):
+    return wl.workload4(n_faces=1500, device=dev, dtype=torch.float32)
+
+
+@pytest.fixture(scope="module")
+def mixed64(dev):
+    return wl.workload4(n_faces=600, device=dev, dtype=torch.float64, seed=99)
+
+
+def build_ops(mb):
+    return {key: api.build_transfer_operator(key[0], key[1], key[2], key[3]) for key in mb.groups()}
+
+
+def batches_of(mb, ops):
+    return [(ops[key], *mb.subset(idx)) for key, idx in mb.groups().items()]
+
+
+def per_batch_reference(mb, ops, mode):
+    coarse, fine = mb.coarse.clone(), mb.fine.clone()
+    for key, idx in mb.groups().items():
+        o, s, co, fo = mb.subset(idx)
+        if key[0] == 0:
+            api.interpolate_faces(ops[key], o, s, co, fo, mb.U, mb.coarse, fine, mode=mode)
+        else:
+            api.restrict_faces(ops[key], o, s, co, fo, mb.U, mb.fine, coarse, mode=mode)
+    torch.cuda.synchronize()
+    return coarse, fine
+
+
+def run_plan(mb, ops, mode, schedule=None):
+    coarse, fine = mb.coarse.clone(), mb.fine.clone()
+    # The plan reads and writes the same pools: interpolated faces read coarse
+    # and write fine, restricted faces read fine and write coarse; faces are
+    # independent, so one launch is race-free.
+    plan = api.build_transfer_plan(batches_of(mb, ops), mb.U, coarse, fine, mode=mode)
+    if schedule is not None:
+        plan.schedule = schedule
+    plan.run()
+    torch.cuda.synchronize()
+    return plan, coarse, fine
+
+
+@pytest.mark.parametrize("mode", [api.FT_F32, api.FT_F32_BF16X3, api.FT_F32_BF16X6])
+def test_plan_equals_per_batch_calls_f32(mixed32, mode):
+    ops = build_ops(mixed32)
+    rc, rf = per_batch_reference(mixed32, ops, mode)
+    _, pc, pf = run_plan(mixed32, ops, mode)
+    assert torch.equal(pc, rc) and torch.equal(pf, rf)
+    for op in ops.values():
+        assert op.errors() == 0
+
+
+def test_plan_equals_per_batch_calls_f64_and_oracle(mixed64):
+    ops = build_ops(mixed64)
+    rc, rf = per_batch_reference(mixed64, ops, None)
+    _, pc, pf = run_plan(mixed64, ops, None)
+    assert torch.equal(pc, rc) and torch.equal(pf, rf)
+    # oracle on up to 4 faces of every (direction, scheme, p, k) group
+    coarse_in = mixed64.coarse.cpu().numpy()
+    fine_in = mixed64.fine.cpu().numpy()
+    pc_np, pf_np = pc.cpu().numpy(), pf.cpu().numpy()
+    co = mixed64.coarse_offset.cpu().numpy()
+    fo = mixed64.fine_offset.cpu().numpy()
+    orient = mixed64.orientation.cpu().numpy()
+    sub = mixed64.subface.cpu().numpy()
+    U = mixed64.U
+    for (d, sch, p, k), idx in mixed64.groups().items():
+        for f in idx[:4].tolist():
+            rows, W = oracle.transfer_operator(d, sch, p, k, int(orient[f]), int(sub[f]))
+            ncell = 2 * k * p * p
+            if d == 0:
+                x = coarse_in[co[f]:co[f] + ncell * U].reshape(ncell, U)
+                got = pf_np[fo[f]:fo[f] + ncell * U].reshape(ncell, U)[rows]
+            else:
+                x = fine_in[fo[f]:fo[f] + ncell * U].reshape(ncell, U)
+                got = pc_np[co[f]:co[f] + ncell * U].reshape(ncell, U)[rows]
+            want = W @ x
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_every_schedule_gives_identical_bits(mixed32):
+    ops = build_ops(mixed32)
+    _, c0, f0 = run_plan(mixed32, ops, api.FT_F32_BF16X6)
+    for sch in (api.pack_schedule(1, 1), api.pack_schedule(2, 3, 1, 0), api.pack_schedule(4, 16, 1, 1),
+                api.pack_schedule(4, 64, 0, 1)):
+        _, c, f = run_plan(mixed32, ops, api.FT_F32_BF16X6, sch)
+        assert torch.equal(c, c0) and torch.equal(f, f0)
+
+
+def test_autotune_picks_a_valid_schedule(mixed32):
+    ops = build_ops(mixed32)
+    coarse, fine = mixed32.coarse.clone(), mixed32.fine.clone()
+    plan = api.build_transfer_plan(batches_of(mixed32, ops), mixed32.U, coarse, fine, mode=api.FT_F32)
+    best, ms = plan.autotune(reps=2)
+    sch = api.unpack_schedule(best)
+    assert sch["waves_per_block"] in (2, 4) and sch["blocks_per_cu"] in (2, 4, 8, 16)
+    assert plan.schedule == best and ms > 0
+    rc, rf = per_batch_reference(mixed32, ops, api.FT_F32)
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(coarse, rc) and torch.equal(fine, rf)
+
+
+def test_graph_replays_equal_eager_runs(mixed32):
+    ops = build_ops(mixed32)
+    coarse, fine = mixed32.coarse.clone(), mixed32.fine.clone()
+    plan = api.build_transfer_plan(batches_of(mixed32, ops), mixed32.U, coarse, fine, mode=api.FT_F32_BF16X3)
+    plan.run()
+    torch.cuda.synchronize()
+    eager_c, eager_f = coarse.clone(), fine.clone()
+    graph = plan.capture(steps=1)
+    for rep in range(4):
+        coarse.copy_(mixed32.coarse)  # eager work between replays
+        fine.copy_(mixed32.fine)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(coarse, eager_c) and torch.equal(fine, eager_f), rep
+
+
+def _shared_face_setup(dev, dtype):
+    """Nine fine faces of one coarse face (so interpolation reads what
+    restriction writes), three copies side by side."""
+    p, k, U = 9, 3, 17
+    base = wl.uniform_faces(27, p, k, U, seed=31, device=dev, dtype=dtype)
+    E = base.face_elems
+    sub = (torch.arange(27) % 9).to(torch.int8).to(dev)
+    orient = torch.tensor([1] * 9 + [3] * 9 + [5] * 9, dtype=torch.int8, device=dev)
+    coff = ((torch.arange(27) // 9) * E).to(torch.int64).to(dev)
+    foff = (torch.arange(27) * E).to(torch.int64).to(dev)
+    coarse = base.coarse[: 3 * E].clone()
+    return p, k, U, orient, sub, coff, foff, coarse, base.fine.clone()
+
+
+def test_restrict_first_plan_and_multi_step_graph(dev):
+    p, k, U, orient, sub, coff, foff, coarse0, fine0 = _shared_face_setup(dev, torch.float64)
+    rop = api.build_transfer_operator(1, 3, p, k)
+    iop = api.build_transfer_operator(0, 3, p, k)
+    # eager reference: restrict then interpolate, three steps
+    rc, rf = coarse0.clone(), fine0.clone()
+    for _ in range(3):
+        api.restrict_faces(rop, orient, sub, coff, foff, U, rf, rc)
+        api.interpolate_faces(iop, orient, sub, coff, foff, U, rc, rf)
+    torch.cuda.synchronize()
+    coarse, fine = coarse0.clone(), fine0.clone()
+    plan = api.build_transfer_plan([(iop, orient, sub, coff, foff), (rop, orient, sub, coff, foff)], U, coarse, fine,
+                                   flags=api.FT_PLAN_RESTRICT_FIRST)
+    graph = plan.capture(steps=3)
+    for rep in range(3):
+        coarse.copy_(coarse0)
+        fine.copy_(fine0)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(coarse, rc) and torch.equal(fine, rf), rep
+    # and the plan run eagerly three times
+    coarse.copy_(coarse0)
+    fine.copy_(fine0)
+    for _ in range(3):
+        plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(coarse, rc) and torch.equal(fine, rf)
