@@ -238,9 +238,14 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
 int run_transfer_plan(const ft_plan* plan, void* stream);
 
 /* Schedule of a plan, packed as waves_per_block | blocks_per_cu << 8 |
- * xcd_remap << 16 | heavy_first << 17 (waves_per_block in {1, 2, 4},
- * blocks_per_cu in 1..64).  Every schedule computes bitwise identical
- * results (each output's summation order is fixed by the operator). */
+ * xcd_remap << 16 | heavy_first << 17 | persistent << 18 (waves_per_block
+ * in {1, 2, 4}, blocks_per_cu in 1..64).  persistent = 1: a grid of
+ * blocks_per_cu blocks per compute unit walks all work items with a grid
+ * stride; persistent = 0: one wave per work item (blocks_per_cu unused).
+ * xcd_remap gives every XCD a contiguous range of items; heavy_first orders
+ * the batches by decreasing cost per item.  Every schedule computes bitwise
+ * identical results (each output's summation order is fixed by the
+ * operator). */
 int transfer_plan_set_schedule(ft_plan* plan, int64_t schedule);
 int transfer_plan_get_schedule(const ft_plan* plan, int64_t* schedule);
 

@@ -174,13 +174,14 @@ def transfer_version():
 FT_PLAN_RESTRICT_FIRST = 1
 
 
-def pack_schedule(waves_per_block=4, blocks_per_cu=8, xcd_remap=0, heavy_first=0):
-    return waves_per_block | (blocks_per_cu << 8) | (xcd_remap << 16) | (heavy_first << 17)
+def pack_schedule(waves_per_block=4, blocks_per_cu=8, xcd_remap=0, heavy_first=0, persistent=1):
+    return (waves_per_block | (blocks_per_cu << 8) | (xcd_remap << 16) | (heavy_first << 17)
+            | (persistent << 18))
 
 
 def unpack_schedule(s):
     return {"waves_per_block": s & 0xFF, "blocks_per_cu": (s >> 8) & 0xFF,
-            "xcd_remap": (s >> 16) & 1, "heavy_first": (s >> 17) & 1}
+            "xcd_remap": (s >> 16) & 1, "heavy_first": (s >> 17) & 1, "persistent": (s >> 18) & 1}
 
 
 class TransferPlan:

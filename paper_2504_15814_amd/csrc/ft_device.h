@@ -34,17 +34,33 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Read-only data reached through pointers that were themselves read from
+// memory (an operator view, its tables, a plan's descriptor arrays) is
+// accessed through the constant address space: wave-uniform reads then go
+// through the scalar cache (s_load) instead of per-lane flat loads.
+#define FT_CONST __attribute__((address_space(4)))
+template <typename P>
+__device__ __forceinline__ const FT_CONST P* cptr(const P* p) {
+  return (const FT_CONST P*)p;
+}
+
 // DIR 0: interpolation (src = coarse, dst = fine).  DIR 1: restriction
 // (src = fine, dst = coarse).  R rows per anchor; EC anchors per axis (0 = read
 // from the operator); COPY is the exact-copy row (its source is stencil entry
 // 0 of every block) or -1.  T storage, A accumulator, W weight type.
 template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W>
 __device__ __forceinline__ void apply_item(
-    const DevOp* __restrict__ op, const int face, const int e,
-    const int8_t* __restrict__ orientation, const int8_t* __restrict__ subface,
-    const int64_t* __restrict__ src_offset, const int64_t* __restrict__ dst_offset, const int U,
+    const DevOp* __restrict__ op_, const int face, const int e,
+    const int8_t* __restrict__ orientation_, const int8_t* __restrict__ subface_,
+    const int64_t* __restrict__ src_offset_, const int64_t* __restrict__ dst_offset_, const int U,
     const T* __restrict__ src, const int64_t src_elems, T* __restrict__ dst,
-    const int64_t dst_elems, const W* __restrict__ weights, int* __restrict__ errors) {
+    const int64_t dst_elems, const W* __restrict__ weights_, int* __restrict__ errors) {
+  const FT_CONST DevOp* op = cptr(op_);
+  const FT_CONST int8_t* orientation = cptr(orientation_);
+  const FT_CONST int8_t* subface = cptr(subface_);
+  const FT_CONST int64_t* src_offset = cptr(src_offset_);
+  const FT_CONST int64_t* dst_offset = cptr(dst_offset_);
+  const FT_CONST W* weights = cptr(weights_);
   constexpr int kGroup = 4;  // stencil loads in flight per wave before their FMAs
   const int lane = threadIdx.x & 63;
   const int E = EC > 0 ? EC : op->E;
@@ -82,8 +98,8 @@ __device__ __forceinline__ void apply_item(
 
   const T* __restrict__ sp = src + so;
   T* __restrict__ dp = dst + dof;
-  const int* __restrict__ pts = op->stencil + start;
-  const W* __restrict__ wts = weights + (int64_t)start * R;
+  const FT_CONST int* pts = cptr(op->stencil) + start;
+  const FT_CONST W* wts = weights + (int64_t)start * R;
 
   for (int u0 = 0; u0 < U; u0 += 64) {
     const int u = u0 + lane;
@@ -106,7 +122,7 @@ __device__ __forceinline__ void apply_item(
       if (COPY >= 0 && q == 0) copy_val = x[0];
 #pragma unroll
       for (int j = 0; j < kGroup; ++j) {
-        const W* __restrict__ w = wts + (q + j) * R;
+        const FT_CONST W* w = wts + (q + j) * R;
 #pragma unroll
         for (int r = 0; r < R; ++r)
           if (r != COPY) acc[r] = fma(A(w[r]), x[j], acc[r]);
@@ -118,7 +134,7 @@ __device__ __forceinline__ void apply_item(
       const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
       const A x = A(sp[(int64_t)cell * U + uu]);
       if (COPY >= 0 && q == 0) copy_val = x;
-      const W* __restrict__ w = wts + q * R;
+      const FT_CONST W* w = wts + q * R;
 #pragma unroll
       for (int r = 0; r < R; ++r)
         if (r != COPY) acc[r] = fma(A(w[r]), x, acc[r]);
@@ -145,12 +161,17 @@ __device__ __forceinline__ void apply_item(
 // tile_all: the block's LDS transpose tiles, one per wave (wave_slot < 4).
 template <int R, int EC, int TERMS>
 __device__ __forceinline__ void mfma_item(
-    const DevOp* __restrict__ op, const int face, const int e, const int wave_slot,
-    float (*tile_all)[32][65], const int8_t* __restrict__ orientation,
-    const int8_t* __restrict__ subface, const int64_t* __restrict__ src_offset,
-    const int64_t* __restrict__ dst_offset, const int U, const float* __restrict__ src,
+    const DevOp* __restrict__ op_, const int face, const int e, const int wave_slot,
+    float (*tile_all)[32][65], const int8_t* __restrict__ orientation_,
+    const int8_t* __restrict__ subface_, const int64_t* __restrict__ src_offset_,
+    const int64_t* __restrict__ dst_offset_, const int U, const float* __restrict__ src,
     const int64_t src_elems, float* __restrict__ dst, const int64_t dst_elems,
     int* __restrict__ errors) {
+  const FT_CONST DevOp* op = cptr(op_);
+  const FT_CONST int8_t* orientation = cptr(orientation_);
+  const FT_CONST int8_t* subface = cptr(subface_);
+  const FT_CONST int64_t* src_offset = cptr(src_offset_);
+  const FT_CONST int64_t* dst_offset = cptr(dst_offset_);
   constexpr int COPY = 13;  // (g, tb, tc) = (1, 1, 1): the coarse centre itself
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, col = lane & 31;
@@ -182,8 +203,8 @@ __device__ __forceinline__ void mfma_item(
   const int anchor_cell = anc_b * st.sb + anc_c * st.sc + nbase * st.sa;
   const int dst_cell0 = nbase * st.sa + 3 * eb * st.sb + 3 * ec * st.sc;
 
-  const bf16x8* __restrict__ wt = reinterpret_cast<const bf16x8*>(op->wbf16);
-  const int* __restrict__ pts = op->stencil + start;
+  const FT_CONST bf16x8* wt = cptr(reinterpret_cast<const bf16x8*>(op->wbf16));
+  const FT_CONST int* pts = cptr(op->stencil) + start;
   int copy_cell;
   {
     int n, db, dc;

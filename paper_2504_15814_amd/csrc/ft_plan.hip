@@ -4,10 +4,8 @@
 //
 // Device side: a plan phase is a table of segments, one per batch, each a
 // contiguous range of (face, anchor) work items.  A fixed grid of waves walks
-// the items with a grid stride; since a wave's items only increase, it
-// advances its segment cursor linearly (amortised O(1) per item) and
-// dispatches to the same per-item bodies as the per-batch kernels
-// (ft_device.h).
+// the items with a grid stride, segment by segment, and runs the same
+// per-item bodies as the per-batch kernels (ft_device.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,12 +36,43 @@ struct PlanSeg {
   int anchors;
 };
 
+// One work item of a plan segment, for one kind of operator.
+template <typename T, int MODE, int KIND>
+__device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const int face_, const int e_,
+                                       const int wave, float (*tile_all)[32][65], const int U,
+                                       T* __restrict__ coarse, const int64_t coarse_elems,
+                                       T* __restrict__ fine, const int64_t fine_elems) {
+  const int face = __builtin_amdgcn_readfirstlane(face_);
+  const int e = __builtin_amdgcn_readfirstlane(e_);
+  const DevOp* __restrict__ op = S->op;
+  const FT_CONST DevOp* cop = cptr(op);
+  if constexpr (KIND == kInterp18 || KIND == kInterp27) {
+    constexpr int R = KIND == kInterp18 ? 18 : 27;
+    if constexpr (MODE == 0)
+      apply_item<0, R, 0, 13, T, T, T>(
+          op, face, e, S->orientation, S->subface, S->coarse_offset, S->fine_offset, U, coarse,
+          coarse_elems, fine, fine_elems,
+          (const T*)(sizeof(T) == 8 ? (const void*)cop->w64 : (const void*)cop->w32), S->errors);
+    else
+      mfma_item<R, 0, MODE>(op, face, e, wave, tile_all, S->orientation, S->subface,
+                            S->coarse_offset, S->fine_offset, U, (const float*)coarse,
+                            coarse_elems, (float*)fine, fine_elems, S->errors);
+  } else {
+    constexpr int R = (KIND == kRestrict2Inject || KIND == kRestrict2Plain) ? 2 : 3;
+    constexpr int COPY = (KIND == kRestrict2Inject || KIND == kRestrict3Inject) ? 0 : -1;
+    apply_item<1, R, 0, COPY, T, double, double>(op, face, e, S->orientation, S->subface,
+                                                 S->fine_offset, S->coarse_offset, U, fine,
+                                                 fine_elems, coarse, coarse_elems, cop->w64,
+                                                 S->errors);
+  }
+}
+
 // MODE 0: interpolation on the vector ALUs in precision T; MODE 3 / 6:
 // float32 interpolation on the matrix cores with that many bfloat16 product
 // terms.  Restriction always sums in float64.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ segs,
-                                                   const int64_t total, const int wpb,
+                                                   const int nseg, const int wpb,
                                                    const int remap, const int U,
                                                    T* __restrict__ coarse, const int64_t coarse_elems,
                                                    T* __restrict__ fine, const int64_t fine_elems) {
@@ -57,67 +86,76 @@ __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ s
     if (b < full) b = (b % 8) * per + b / 8;
   }
   const int64_t stride = (int64_t)gridDim.x * wpb;
-  int sg = 0;
-  for (int64_t it = b * wpb + wave; it < total; it += stride) {
-    while (it >= segs[sg].item_end) ++sg;
+  const int64_t w = b * wpb + wave;
+  // Segments in order; inside a segment this wave takes every stride-th item
+  // (continuing the grid-stride sequence across segments).  The kind switch
+  // sits outside the item loop so each loop holds a single body.
+  for (int sg = 0; sg < nseg; ++sg) {
     const PlanSeg* __restrict__ S = segs + sg;
+    const int64_t item0 = S->item0, item_end = S->item_end;
+    int64_t first = item0 + ((w - item0) % stride + stride) % stride;
+    if (first >= item_end) continue;
     const int anchors = S->anchors;
-    const int64_t local = it - S->item0;
-    const int face = (int)(local / anchors);
-    const int e = (int)(local - (int64_t)face * anchors);
-    const DevOp* __restrict__ op = S->op;
     switch (S->kind) {
-      case kInterp18:
-        if constexpr (MODE == 0)
-          apply_item<0, 18, 0, 13, T, T, T>(op, face, e, S->orientation, S->subface,
-                                            S->coarse_offset, S->fine_offset, U, coarse,
-                                            coarse_elems, fine, fine_elems,
-                                            (const T*)(sizeof(T) == 8 ? (const void*)op->w64
-                                                                      : (const void*)op->w32),
-                                            S->errors);
-        else
-          mfma_item<18, 0, MODE>(op, face, e, wave, tile_all, S->orientation, S->subface,
-                                 S->coarse_offset, S->fine_offset, U, (const float*)coarse,
-                                 coarse_elems, (float*)fine, fine_elems, S->errors);
-        break;
-      case kInterp27:
-        if constexpr (MODE == 0)
-          apply_item<0, 27, 0, 13, T, T, T>(op, face, e, S->orientation, S->subface,
-                                            S->coarse_offset, S->fine_offset, U, coarse,
-                                            coarse_elems, fine, fine_elems,
-                                            (const T*)(sizeof(T) == 8 ? (const void*)op->w64
-                                                                      : (const void*)op->w32),
-                                            S->errors);
-        else
-          mfma_item<27, 0, MODE>(op, face, e, wave, tile_all, S->orientation, S->subface,
-                                 S->coarse_offset, S->fine_offset, U, (const float*)coarse,
-                                 coarse_elems, (float*)fine, fine_elems, S->errors);
-        break;
-      case kRestrict2Inject:
-        apply_item<1, 2, 0, 0, T, double, double>(op, face, e, S->orientation, S->subface,
-                                                  S->fine_offset, S->coarse_offset, U, fine,
-                                                  fine_elems, coarse, coarse_elems, op->w64,
-                                                  S->errors);
-        break;
-      case kRestrict2Plain:
-        apply_item<1, 2, 0, -1, T, double, double>(op, face, e, S->orientation, S->subface,
-                                                   S->fine_offset, S->coarse_offset, U, fine,
-                                                   fine_elems, coarse, coarse_elems, op->w64,
-                                                   S->errors);
-        break;
-      case kRestrict3Inject:
-        apply_item<1, 3, 0, 0, T, double, double>(op, face, e, S->orientation, S->subface,
-                                                  S->fine_offset, S->coarse_offset, U, fine,
-                                                  fine_elems, coarse, coarse_elems, op->w64,
-                                                  S->errors);
-        break;
-      default:
-        apply_item<1, 3, 0, -1, T, double, double>(op, face, e, S->orientation, S->subface,
-                                                   S->fine_offset, S->coarse_offset, U, fine,
-                                                   fine_elems, coarse, coarse_elems, op->w64,
-                                                   S->errors);
-        break;
+#define FT_PLAN_LOOP(KIND)                                                                     \
+  for (int64_t it = first; it < item_end; it += stride) {                                      \
+    const int local = (int)(it - item0); /* segments hold < 2^31 items */                      \
+    const int face = local / anchors;                                                          \
+    plan_item<T, MODE, KIND>(S, face, local - face * anchors, wave, tile_all, U, coarse,       \
+                             coarse_elems, fine, fine_elems);                                  \
+  }                                                                                            \
+  break;
+      case kInterp18: FT_PLAN_LOOP(kInterp18)
+      case kInterp27: FT_PLAN_LOOP(kInterp27)
+      case kRestrict2Inject: FT_PLAN_LOOP(kRestrict2Inject)
+      case kRestrict2Plain: FT_PLAN_LOOP(kRestrict2Plain)
+      case kRestrict3Inject: FT_PLAN_LOOP(kRestrict3Inject)
+      default: FT_PLAN_LOOP(kRestrict3Plain)
+#undef FT_PLAN_LOOP
     }
+  }
+}
+
+// Non-persistent form of the same fused launch: the grid covers every work
+// item once, and each wave finds its segment by binary search over the
+// segment table (a handful of scalar loads).  Without the grid-stride loop
+// the bodies keep their stand-alone register budget.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restrict__ segs,
+                                                        const int nseg, const int64_t total,
+                                                        const int wpb, const int remap,
+                                                        const int U, T* __restrict__ coarse,
+                                                        const int64_t coarse_elems,
+                                                        T* __restrict__ fine,
+                                                        const int64_t fine_elems) {
+  __shared__ float tile_all[MODE ? 4 : 1][32][65];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t b = blockIdx.x;
+  if (remap) {
+    const int64_t nb = gridDim.x, per = nb / 8, full = per * 8;
+    if (b < full) b = (b % 8) * per + b / 8;
+  }
+  const int64_t it = b * wpb + wave;
+  if (it >= total) return;
+  int lo = 0, hi = nseg - 1;  // first segment whose item_end exceeds it
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (it >= segs[mid].item_end) lo = mid + 1; else hi = mid;
+  }
+  // The search is wave-uniform; say so, so that the segment and the operator
+  // it points to are read through the scalar cache.
+  const PlanSeg* __restrict__ S = segs + __builtin_amdgcn_readfirstlane(lo);
+  const int local = (int)(it - S->item0);
+  const int anchors = S->anchors;
+  const int face = local / anchors;
+  const int e = local - face * anchors;
+  switch (S->kind) {
+    case kInterp18: plan_item<T, MODE, kInterp18>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp27: plan_item<T, MODE, kInterp27>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict2Inject: plan_item<T, MODE, kRestrict2Inject>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict2Plain: plan_item<T, MODE, kRestrict2Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict3Inject: plan_item<T, MODE, kRestrict3Inject>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    default: plan_item<T, MODE, kRestrict3Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
   }
 }
 
@@ -157,6 +195,7 @@ int wpb_of(int64_t s) { return (int)(s & 0xff); }
 int bpc_of(int64_t s) { return (int)((s >> 8) & 0xff); }
 int remap_of(int64_t s) { return (int)((s >> 16) & 1); }
 int heavy_of(int64_t s) { return (int)((s >> 17) & 1); }
+int persistent_of(int64_t s) { return (int)((s >> 18) & 1); }
 
 int plan_kind(const ft_operator* op) {
   if (op->direction == FT_INTERPOLATE) return op->k == 2 ? ft::kInterp18 : ft::kInterp27;
@@ -232,9 +271,17 @@ template <typename T, int MODE>
 hipError_t launch_phase(const ft_plan* plan, int ph, hipStream_t stream) {
   const int wpb = wpb_of(plan->schedule);
   const int64_t want = (plan->total[ph] + wpb - 1) / wpb;
+  if (!persistent_of(plan->schedule)) {
+    if (want > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((ft::plan_item_kernel<T, MODE>), dim3((unsigned)want), dim3(64 * wpb), 0,
+                       stream, plan->d_segs[ph], plan->nseg[ph], plan->total[ph], wpb,
+                       remap_of(plan->schedule), plan->U, static_cast<T*>(plan->coarse),
+                       plan->coarse_elems, static_cast<T*>(plan->fine), plan->fine_elems);
+    return hipGetLastError();
+  }
   const int64_t blocks = std::min<int64_t>(want, (int64_t)plan->n_cu * bpc_of(plan->schedule));
   hipLaunchKernelGGL((ft::plan_kernel<T, MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0, stream,
-                     plan->d_segs[ph], plan->total[ph], wpb, remap_of(plan->schedule), plan->U,
+                     plan->d_segs[ph], plan->nseg[ph], wpb, remap_of(plan->schedule), plan->U,
                      static_cast<T*>(plan->coarse), plan->coarse_elems,
                      static_cast<T*>(plan->fine), plan->fine_elems);
   return hipGetLastError();
@@ -257,7 +304,7 @@ int run_plan(const ft_plan* plan, hipStream_t stream) {
 
 bool valid_schedule(int64_t s) {
   const int w = wpb_of(s), b = bpc_of(s);
-  return (w == 1 || w == 2 || w == 4) && b >= 1 && b <= 64 && (s >> 18) == 0;
+  return (w == 1 || w == 2 || w == 4) && b >= 1 && b <= 64 && (s >> 19) == 0;
 }
 
 }  // namespace
@@ -285,8 +332,8 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
       return pfail(FT_ERR_INVALID, "batch operator is host-only or on another device");
     if (b.n_faces > 0 && (!b.orientation || !b.subface || !b.coarse_offset || !b.fine_offset))
       return pfail(FT_ERR_INVALID, "batch with NULL descriptor arrays");
-    if (b.n_faces * (int64_t)b.op->E * b.op->E > ((int64_t)1 << 40))
-      return pfail(FT_ERR_UNSUPPORTED, "batch too large");
+    if (b.n_faces * (int64_t)b.op->E * b.op->E >= ((int64_t)1 << 31))
+      return pfail(FT_ERR_UNSUPPORTED, "batch too large (faces x anchors must stay below 2^31)");
     if (dtype >= FT_F32_BF16X3 && b.op->direction == FT_INTERPOLATE && !b.op->d_wbf16)
       return pfail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
   }
@@ -304,7 +351,7 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     plan->n_cu = ncu;
-  plan->schedule = 4 | (8 << 8);  // 4 waves per block, 8 blocks per CU
+  plan->schedule = 4 | (1 << 8);  // 4 waves per block, one wave per work item
   const int rc = upload_tables(plan);
   if (rc != FT_OK) {
     free_tables(plan);
@@ -352,12 +399,19 @@ int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_
   int64_t best = orig;
   double best_t = INFINITY;
   int rc = FT_OK;
-  for (int heavy = 0; heavy < 2 && rc == FT_OK; ++heavy)
-    for (int remap = 0; remap < 2 && rc == FT_OK; ++remap)
-      for (int wpb : {2, 4})
-        for (int bpc : {2, 4, 8, 16}) {
-          const int64_t sch = wpb | ((int64_t)bpc << 8) | ((int64_t)remap << 16) |
-                              ((int64_t)heavy << 17);
+  // Candidates: one wave per work item (blocks_per_cu unused) and the
+  // persistent grid-stride form with 2..16 blocks per CU.
+  std::vector<int64_t> cands;
+  for (int heavy = 0; heavy < 2; ++heavy)
+    for (int remap = 0; remap < 2; ++remap)
+      for (int wpb : {2, 4}) {
+        cands.push_back(wpb | (1LL << 8) | ((int64_t)remap << 16) | ((int64_t)heavy << 17));
+        for (int bpc : {2, 4, 8, 16})
+          cands.push_back(wpb | ((int64_t)bpc << 8) | ((int64_t)remap << 16) |
+                          ((int64_t)heavy << 17) | (1LL << 18));
+      }
+  for (const int64_t sch : cands) {
+        {
           if ((rc = transfer_plan_set_schedule(plan, sch)) != FT_OK) break;
           if ((rc = run_plan(plan, s)) != FT_OK) break;  // warm-up
           (void)hipEventRecord(e0, s);
@@ -376,6 +430,7 @@ int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_
             best = sch;
           }
         }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != FT_OK) {

@@ -174,5 +174,6 @@ def test_plan_checks_happen_on_host():
 
 
 def test_schedule_packing_roundtrip():
-    s = api.pack_schedule(2, 16, 1, 1)
-    assert api.unpack_schedule(s) == {"waves_per_block": 2, "blocks_per_cu": 16, "xcd_remap": 1, "heavy_first": 1}
+    s = api.pack_schedule(2, 16, 1, 1, 0)
+    assert api.unpack_schedule(s) == {"waves_per_block": 2, "blocks_per_cu": 16, "xcd_remap": 1, "heavy_first": 1,
+                                      "persistent": 0}
