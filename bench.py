@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--batched-faces", type=int, default=50000,
                     help="faces of the uneven-mix workload run as one plan (0 disables it)")
+    ap.add_argument("--mesh-meshes", type=int, default=3,
+                    help="independently seeded 3-level AMR meshes in the per-step leg (0 disables it)")
+    ap.add_argument("--mesh-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -167,6 +170,60 @@ def batched_leg(args, torch, api, wl):
                       "max_rel_err_vs_f64": max(errs)}
         del graph, plan, pc, pf
     return out
+
+
+def mesh_leg(args, torch, api, wl):
+    """Full per-step transfer on synthetic 3-level AMR meshes (Taylor-3,
+    p=9, k=3, U=59): every step restricts all hanging faces into their shared
+    coarse faces and then interpolates all fine halos from them.  Plain FP64
+    (two launches per step, eager) versus the mixed form (float32 plan,
+    split-bfloat16 matrix-core interpolation with compensation) with all
+    steps captured in one HIP graph."""
+    mf = wl.workload5(n_meshes=args.mesh_meshes, device="cuda:0", dtype=torch.float64)
+    U, steps = mf.U, args.mesh_steps
+    rop = api.build_transfer_operator(api.FT_RESTRICT, 3, mf.p, mf.k)
+    iop = api.build_transfer_operator(api.FT_INTERPOLATE, 3, mf.p, mf.k)
+    d = (mf.orientation, mf.subface, mf.coarse_offset, mf.fine_offset)
+    produced = mf.n * (9 * mf.k + mf.k) * (mf.p // 3) ** 2 * U
+
+    c64, f64 = mf.coarse.clone(), mf.fine.clone()
+
+    def step64():
+        api.restrict_faces(rop, *d, U, f64, c64)
+        api.interpolate_faces(iop, *d, U, c64, f64)
+
+    step64()
+    torch.cuda.synchronize()
+    ref1_c, ref1_f = c64.clone(), f64.clone()
+    ms64, _ = run_steps([("f64_step", step64)], steps, args.warmup, torch)
+
+    c32, f32 = mf.coarse.float(), mf.fine.float()
+    plan = api.build_transfer_plan([(rop, *d), (iop, *d)], U, c32, f32, mode=api.FT_F32_BF16X6,
+                                   flags=api.FT_PLAN_RESTRICT_FIRST)
+    plan.run()
+    torch.cuda.synchronize()
+    err = max(float((c32.double() - ref1_c).abs().max() / ref1_c.abs().max()),
+              float((f32.double() - ref1_f).abs().max() / ref1_f.abs().max()))
+    best, _ = plan.autotune(reps=3)
+    graph = plan.capture(steps=steps)
+    graph.launch()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    graph.launch()
+    b.record()
+    torch.cuda.synchronize()
+    ms_mixed = a.elapsed_time(b) / steps
+    return {"workload": f"{args.mesh_meshes} seeded 3-level AMR meshes (27^3 base patches, refinement "
+                        "radii 0.3 / 0.1), Taylor-3, p=9, k=3, U=59, restrict then interpolate",
+            "hanging_faces": mf.n, "coarse_faces": mf.n_coarse,
+            "faces_per_fine_level": {str(kk): v for kk, v in sorted(mf.transitions.items())},
+            "steps": steps, "ghost_cell_unknowns_per_step": produced,
+            "f64_ms_per_step": ms64, "mixed_graph_ms_per_step": ms_mixed,
+            "mixed_value": produced / (ms_mixed * 1e-3), "f64_value": produced / (ms64 * 1e-3),
+            "speedup": ms64 / ms_mixed, "mixed_max_rel_err_one_step": err,
+            "schedule": api.unpack_schedule(best)}
 
 
 def cpu_baseline(batch, n_faces, torch):
@@ -318,6 +375,9 @@ def main():
 
     if args.batched_faces > 0:
         result["batched"] = batched_leg(args, torch, api, wl)
+
+    if args.mesh_meshes > 0:
+        result["mesh"] = mesh_leg(args, torch, api, wl)
 
     if args.cpu_faces > 0:
         result["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_faces, n), torch)

@@ -366,3 +366,176 @@ def workload4(n_faces=50000, device="cpu", dtype=torch.float32, U=59, seed=SEED_
                 mb.coarse[where] = vc.reshape(-1).to(dtype)
                 mb.fine[where] = vf.reshape(-1).to(dtype)
     return mb
+
+
+# ---------------------------------------------------------------------------
+# Workload 5: hanging faces of synthetic 3-level AMR meshes
+# ---------------------------------------------------------------------------
+@dataclass
+class MeshFaces:
+    """Hanging faces of an adaptive Cartesian mesh (three-partitioning, 2:1
+    balanced).  Coarse face buffers are shared by the nine fine faces that
+    cover them; every fine face owns its buffer."""
+
+    p: int
+    k: int
+    U: int
+    n_coarse: int
+    orientation: torch.Tensor  # int8 [n]
+    subface: torch.Tensor  # int8 [n]
+    coarse_offset: torch.Tensor  # int64 [n]
+    fine_offset: torch.Tensor  # int64 [n]
+    coarse: torch.Tensor
+    fine: torch.Tensor
+    levels: dict = field(default_factory=dict)  # leaf count per level
+    transitions: dict = field(default_factory=dict)  # hanging faces per fine level
+
+    @property
+    def n(self):
+        return int(self.orientation.numel())
+
+    @property
+    def face_elems(self):
+        return 2 * self.k * self.p * self.p * self.U
+
+
+def amr_leaves(seed, base_level=3, radii=(0.3, 0.1)):
+    """Leaves {(level, i, j, l)} of a unit-cube spacetree: every patch of the
+    base level is split into 3^3 children if its centre lies within radii[0]
+    of either of two centres drawn U[0.3, 0.7]^3, and those children again if
+    within radii[1]; then refined further until neighbours differ by at most
+    one level (2:1 balance)."""
+    gen = np.random.default_rng(seed)
+    centres = gen.uniform(0.3, 0.7, size=(2, 3))
+
+    def near(level, idx, r):
+        h = 3.0 ** -level
+        c = (np.asarray(idx) + 0.5) * h
+        return np.min(np.linalg.norm(centres - c, axis=1)) <= r
+
+    n0 = 3 ** base_level
+    leaves = set()
+    for i in range(n0):
+        for j in range(n0):
+            for l in range(n0):
+                leaves.add((base_level, i, j, l))
+    for depth, r in enumerate(radii):
+        lvl = base_level + depth
+        for leaf in [x for x in leaves if x[0] == lvl and near(lvl, x[1:], r)]:
+            leaves.discard(leaf)
+            for di in range(3):
+                for dj in range(3):
+                    for dl in range(3):
+                        leaves.add((lvl + 1, 3 * leaf[1] + di, 3 * leaf[2] + dj, 3 * leaf[3] + dl))
+    # 2:1 balance: refine any leaf with a face neighbour two or more levels finer.
+    changed = True
+    while changed:
+        changed = False
+        for leaf in sorted(leaves, key=lambda x: -x[0]):
+            lvl, idx = leaf[0], leaf[1:]
+            for ax in range(3):
+                for sgn in (-1, 1):
+                    nb = list(idx)
+                    nb[ax] += sgn
+                    if not (0 <= nb[ax] < 3 ** lvl):
+                        continue
+                    coarse = (lvl - 2, *[v // 9 for v in nb])
+                    if coarse in leaves:
+                        leaves.discard(coarse)
+                        for di in range(3):
+                            for dj in range(3):
+                                for dl in range(3):
+                                    leaves.add((lvl - 1, 3 * coarse[1] + di, 3 * coarse[2] + dj, 3 * coarse[3] + dl))
+                        changed = True
+    return leaves
+
+
+def hanging_faces(leaves):
+    """[(coarse_leaf, fine_leaf, orientation, subface)] for every fine leaf
+    face that touches a leaf one level coarser."""
+    out = []
+    for leaf in leaves:
+        lvl, idx = leaf[0], leaf[1:]
+        for ax in range(3):
+            for sgn in (-1, 1):
+                nb = list(idx)
+                nb[ax] += sgn
+                if not (0 <= nb[ax] < 3 ** lvl) or (lvl, *nb) in leaves:
+                    continue
+                parent = (lvl - 1, *[v // 3 for v in nb])
+                if parent not in leaves:
+                    continue  # finer neighbour: seen from its side
+                b, c = [x for x in range(3) if x != ax]
+                sb = idx[b] - 3 * parent[1 + b]
+                sc = idx[c] - 3 * parent[1 + c]
+                # fine patch on the + side of the face when it lies above it
+                o = ax if sgn < 0 else ax + 3
+                out.append((parent, leaf, o, sb + 3 * sc))
+    return out
+
+
+def workload5(n_meshes=3, p=9, k=3, U=59, device="cpu", dtype=torch.float64, seed=SEED_BASE + 5,
+              base_level=3):
+    """Hanging faces of n_meshes independently seeded 3-level meshes (base
+    level 3: 27^3 patches of p^3 cells), with shared coarse face buffers;
+    bump fields sampled at every cell centre of both buffers."""
+    gen = torch.Generator().manual_seed(seed)
+    fieldfn = bump_field(gen, U)
+    coarse_keys, records = {}, []
+    levels, transitions = {}, {}
+    for m in range(n_meshes):
+        leaves = amr_leaves(seed * 7 + m, base_level)
+        for lf in leaves:
+            levels[lf[0]] = levels.get(lf[0], 0) + 1
+        for parent, leaf, o, s in sorted(hanging_faces(leaves)):
+            key = (m, parent, o)
+            if key not in coarse_keys:
+                coarse_keys[key] = len(coarse_keys)
+            records.append((coarse_keys[key], m, parent, leaf, o, s))
+            transitions[leaf[0]] = transitions.get(leaf[0], 0) + 1
+    n = len(records)
+    E = 2 * k * p * p * U
+    orient = torch.tensor([r[4] for r in records], dtype=torch.int8)
+    sub = torch.tensor([r[5] for r in records], dtype=torch.int8)
+    coff = torch.tensor([r[0] * E for r in records], dtype=torch.int64)
+    foff = torch.arange(n, dtype=torch.int64) * E
+    mf = MeshFaces(p, k, U, len(coarse_keys), orient.to(device), sub.to(device), coff.to(device),
+                   foff.to(device), torch.zeros(len(coarse_keys) * E, dtype=dtype, device=device),
+                   torch.zeros(n * E, dtype=dtype, device=device), levels, transitions)
+    # Physical placement: the face plane lies between coarse leaf and fine
+    # leaf; the coarse face's lower tangential corner is the coarse leaf's.
+    origin = torch.zeros(n, 3, dtype=torch.float64)
+    hf = torch.zeros(n, dtype=torch.float64)
+    for f, (_, _m, parent, leaf, o, s) in enumerate(records):
+        a = o % 3
+        hc_patch = 3.0 ** -parent[0]
+        hf[f] = 3.0 ** -leaf[0] / p
+        org = [parent[1 + ax] * hc_patch for ax in range(3)]
+        org[a] = (parent[1 + a] + (1 if o < 3 else 0)) * hc_patch
+        origin[f] = torch.tensor(org)
+    dev = device
+    cc = {o: coarse_centres(o, p, k, dev) for o in range(6)}
+    fc = {(o, s): fine_centres(o, p, k, s, dev) for o in range(6) for s in range(9)}
+    ol, sl = orient.tolist(), sub.tolist()
+    filled = torch.zeros(len(coarse_keys), dtype=torch.bool)
+    for f0 in range(0, n, 1024):
+        f1 = min(n, f0 + 1024)
+        idx = range(f0, f1)
+        org = origin[f0:f1].to(dev)[:, None, :]
+        h = hf[f0:f1].to(dev)[:, None, None]
+        pos_f = torch.stack([fc[(ol[i], sl[i])] for i in idx]) * h + org
+        vf = fieldfn(pos_f.reshape(-1, 3)).reshape(f1 - f0, E)
+        mf.fine[f0 * E:f1 * E] = vf.reshape(-1).to(dtype)
+        # coarse buffers: fill once per coarse face, from its first fine face
+        firsts = [i for i in idx if not filled[records[i][0]]]
+        for i in firsts:
+            filled[records[i][0]] = True
+        if firsts:
+            sel = torch.tensor(firsts)
+            orgc = origin[sel].to(dev)[:, None, :]
+            hc = hf[sel].to(dev)[:, None, None]
+            pos_c = torch.stack([cc[ol[i]] for i in firsts]) * hc + orgc
+            vc = fieldfn(pos_c.reshape(-1, 3)).reshape(len(firsts), E)
+            where = (coff[sel].to(dev)[:, None] + torch.arange(E, device=dev)[None, :]).reshape(-1)
+            mf.coarse[where] = vc.reshape(-1).to(dtype)
+    return mf

@@ -1,0 +1,105 @@
+"""One time step on the hanging faces of a synthetic 3-level AMR mesh:
+restriction into the shared coarse faces, then interpolation from them, as a
+restrict-first plan and as captured multi-step graphs, against eager calls
+and against the FP64 oracle (restriction of all nine subfaces of a coarse
+face followed by interpolation from the updated coarse face)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_15814_amd import api
+from paper_2504_15814_amd import workloads as wl
+from tests import gpu_helpers as gh
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mesh(dev):
+    return wl.workload5(n_meshes=1, U=5, device=dev)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return gh.require_gpu()
+
+
+def step_eager(mf, rop, iop, coarse, fine, mode=None):
+    api.restrict_faces(rop, mf.orientation, mf.subface, mf.coarse_offset, mf.fine_offset, mf.U, fine, coarse, mode=mode)
+    api.interpolate_faces(iop, mf.orientation, mf.subface, mf.coarse_offset, mf.fine_offset, mf.U, coarse, fine,
+                          mode=mode)
+
+
+def make_plan(mf, rop, iop, coarse, fine, mode=None):
+    descr = (mf.orientation, mf.subface, mf.coarse_offset, mf.fine_offset)
+    return api.build_transfer_plan([(rop, *descr), (iop, *descr)], mf.U, coarse, fine, mode=mode,
+                                   flags=api.FT_PLAN_RESTRICT_FIRST)
+
+
+@pytest.mark.parametrize("scheme", [1, 3])
+def test_mesh_step_plan_graph_and_oracle(mesh, scheme):
+    mf = mesh
+    rop = api.build_transfer_operator(1, scheme, mf.p, mf.k)
+    iop = api.build_transfer_operator(0, scheme, mf.p, mf.k)
+    ec, ef = mf.coarse.clone(), mf.fine.clone()
+    step_eager(mf, rop, iop, ec, ef)
+    torch.cuda.synchronize()
+    pc, pf = mf.coarse.clone(), mf.fine.clone()
+    plan = make_plan(mf, rop, iop, pc, pf)
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(pc, ec) and torch.equal(pf, ef)
+    assert rop.errors() == 0 and iop.errors() == 0
+
+    # oracle: all nine subfaces of 12 coarse faces, restriction then interpolation
+    o = mf.orientation.cpu().numpy()
+    s = mf.subface.cpu().numpy()
+    co = mf.coarse_offset.cpu().numpy()
+    fo = mf.fine_offset.cpu().numpy()
+    coarse0, fine0 = mf.coarse.cpu().numpy(), mf.fine.cpu().numpy()
+    picks = np.unique(co)[:: max(1, mf.n_coarse // 12)][:12]
+    faces = np.flatnonzero(np.isin(co, picks))
+    assert len(faces) == 9 * len(picks)
+    c1 = oracle.restrict_faces(scheme, mf.p, mf.k, o[faces], s[faces], co[faces], fo[faces], mf.U, fine0, coarse0)
+    f1 = oracle.interpolate_faces(scheme, mf.p, mf.k, o[faces], s[faces], co[faces], fo[faces], mf.U, c1, fine0)
+    E = mf.face_elems
+    got_c, got_f = pc.cpu().numpy(), pf.cpu().numpy()
+    for cidx in picks:
+        a, b = got_c[cidx:cidx + E], c1[cidx:cidx + E]
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+    for f in faces:
+        a, b = got_f[fo[f]:fo[f] + E], f1[fo[f]:fo[f] + E]
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+
+    # five captured steps equal five eager steps, replayed twice
+    for _ in range(4):
+        step_eager(mf, rop, iop, ec, ef)
+    torch.cuda.synchronize()
+    graph = plan.capture(steps=5)
+    for rep in range(2):
+        pc.copy_(mf.coarse)
+        pf.copy_(mf.fine)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(pc, ec) and torch.equal(pf, ef), rep
+
+
+def test_mesh_step_mixed_precision_plan(mesh):
+    """Float32 storage: the Taylor-3 restriction at k = 3 extrapolates with
+    row 1-norms up to ~406, which amplifies the 2^-24 rounding of the stored
+    inputs to ~2.4e-5 of max|x|; interpolation then reads those values."""
+    mf = mesh
+    rop = api.build_transfer_operator(1, 3, mf.p, mf.k)
+    iop = api.build_transfer_operator(0, 3, mf.p, mf.k)
+    ec, ef = mf.coarse.clone(), mf.fine.clone()
+    step_eager(mf, rop, iop, ec, ef)
+    pc, pf = mf.coarse.float(), mf.fine.float()
+    plan = make_plan(mf, rop, iop, pc, pf, mode=api.FT_F32_BF16X6)
+    plan.run()
+    torch.cuda.synchronize()
+    for got, ref in ((pc, ec), (pf, ef)):
+        err = (got.double() - ref).abs().max() / ref.abs().max()
+        assert err < 5e-5
