@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--faces", type=int, default=20000)
-    ap.add_argument("--cpu-faces", type=int, default=4000,
+    ap.add_argument("--cpu-faces", type=int, default=20000,
                     help="faces in the oracle's CPU-baseline sample (0 disables it)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--batched-faces", type=int, default=50000,
@@ -74,21 +74,24 @@ def algorithmic_bytes(op, orientation, subface, U, elem_bytes):
     return int(sum(per[(o, s)] * counts[o, s] for o in range(6) for s in range(9)))
 
 
-def recorded_traffic(kernel_name):
+KERNEL_SOURCES = ("ft_device.h", "ft_kernels.hip", "ft_mfma.hip")
+
+
+def recorded_traffic(kernel_name, mode="f64"):
     """HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) recorded for this kernel
-    in profiles/, or None if the kernel source changed since they were taken."""
+    in profiles/, or None if the kernel sources changed since they were taken."""
     import hashlib
 
-    prof = os.path.join(ROOT, "profiles", "apply_kernel_workload2.md")
-    src = os.path.join(ROOT, "paper_2504_15814_amd", "csrc", "ft_kernels.hip")
+    prof = os.path.join(ROOT, "profiles", "transfer_kernels_workload2.md")
+    csrc = os.path.join(ROOT, "paper_2504_15814_amd", "csrc")
     try:
         text = open(prof).read()
-        block = text.split("```json")[1].split("```")[0]
-        rec = json.loads(block)
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        rec = json.loads(text.split("```json")[1].split("```")[0])
+        cur = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                      for f in KERNEL_SOURCES)).hexdigest()[:16]
         if rec.get("kernel_source_sha256_16") != cur:
             return None
-        k = rec["kernels"][f"f64/{kernel_name}"]
+        k = rec["kernels"][f"{mode}/{kernel_name}"]
         return int(k["read_bytes"] + k["write_bytes"])
     except (OSError, IndexError, KeyError, ValueError):
         return None
