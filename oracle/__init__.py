@@ -17,6 +17,8 @@ fit        Taylor terms and the pinned-constant least-squares fit
 transfer   dense per-subface operators built directly in each physical
            orientation, and their application to batches of faces
            (Section 2, the P / R matrices and their 1/9 segments)
+patches    patches with face halos: face views, the same-level halo copy, and
+           the transfer composed with them (Section 2)
 
 Everything is float64 and written for readability, not speed.
 """
@@ -46,6 +48,7 @@ from .transfer import (
     restrict_faces,
     clear_operator_cache,
 )
+from . import patches
 
 __all__ = [
     "face_axes",
@@ -73,4 +76,5 @@ __all__ = [
     "interpolate_faces",
     "restrict_faces",
     "clear_operator_cache",
+    "patches",
 ]
