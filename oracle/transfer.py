@@ -40,8 +40,11 @@ def _check(scheme, p, k, o, s):
         raise ValueError(f"unknown scheme {scheme}")
     if p < 6 or p % 3:
         raise ValueError(f"p must be a multiple of 3 and >= 6, got {p}")
-    if k not in (2, 3):
-        raise ValueError(f"k must be 2 or 3, got {k}")
+    if k not in (1, 2, 3):
+        raise ValueError(f"k must be 1, 2 or 3, got {k}")
+    if k == 1 and scheme != DLINEAR:
+        # a 3-point Taylor stencil along the normal needs 2k >= 3 layers
+        raise ValueError("k = 1 (finite volumes) is supported by the d-linear scheme only")
     if not (0 <= o < 6 and 0 <= s < 9):
         raise ValueError("orientation in 0..5 and subface in 0..8 required")
 
@@ -102,8 +105,9 @@ def _dlinear_restriction_row(o, p, k, s, target_pos, fine_pos, ext):
     """Averaging restriction (the tensor-product baseline's counterpart):
     mean over the fine columns under the target per tangential axis; along
     the normal the mean of the fine inner layers inside the target when all
-    three exist, else linear extrapolation through the two inner layers
-    farthest from the face."""
+    three exist, else linear extrapolation through the two fine layers
+    deepest into the fine side (the last two inner layers; with k = 1 the
+    single inner layer and the halo layer next to it)."""
     a, b, c = geo.face_axes(o)
     side = 1.0 if geo.fine_on_plus_side(o) else -1.0
     depth_T = side * target_pos[a]  # distance of the target centre into the fine side
@@ -112,13 +116,13 @@ def _dlinear_restriction_row(o, p, k, s, target_pos, fine_pos, ext):
         lo = target_pos[ax] - 1.5
         tang[ax] = [i for i in range(ext[ax]) if lo < fine_pos[ax][i] < lo + 3.0]
         assert len(tang[ax]) == 3
-    inner = [i for i in range(ext[a]) if side * fine_pos[a][i] > 0]
-    inner.sort(key=lambda i: side * fine_pos[a][i])
+    layers = sorted(range(ext[a]), key=lambda i: side * fine_pos[a][i])
+    inner = [i for i in layers if side * fine_pos[a][i] > 0]
     covered = [i for i in inner if abs(side * fine_pos[a][i] - depth_T) < 1.5]
     if len(covered) == 3:
         normal = {i: 1.0 / 3.0 for i in covered}
     else:
-        i1, i2 = inner[-2], inner[-1]
+        i1, i2 = layers[-2], layers[-1]
         d1, d2 = side * fine_pos[a][i1], side * fine_pos[a][i2]
         t = (depth_T - d1) / (d2 - d1)
         normal = {i1: 1.0 - t, i2: t}

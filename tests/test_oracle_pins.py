@@ -262,3 +262,49 @@ def test_convergence_order(direction, scheme, order):
     slope, errs = _convergence_slope(scheme, direction)
     assert abs(slope - order) < 0.25, (slope, errs)
     assert errs[-1] < errs[0]
+
+
+# k = 1 (finite volumes, Section 2): the d-linear scheme only.
+
+
+@pytest.mark.parametrize("p", [6, 9])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_dlinear_k1_reproduces_trilinear_fields(p, direction):
+    rng = np.random.default_rng(77 + p + direction)
+    worst = 0.0
+    for o in range(6):
+        for s in range(9):
+            worst = max(worst, chk.reproduction_error(oracle, 1, p, 1, o, s, rng, direction))
+    assert worst < 1e-12, worst
+
+
+def test_dlinear_k1_rows_and_normal_weights():
+    """Interpolation: the one fine ghost layer lies 1/6 coarse width into the
+    coarse side, between coarse layer 0 (1/2 width in) and the coarse face's
+    fine-side layer (1/2 width out): weights 2/3 and 1/3.  Restriction:
+    the coarse centre 3/2 fine widths in, extrapolated through fine layer 0
+    and the halo layer: 2 and -1 (fixture)."""
+    p, k, o = 6, 1, 0
+    for s in range(9):
+        for direction in (0, 1):
+            rows, W = oracle.transfer_operator(direction, 1, p, k, o, s)
+            assert np.allclose(W.sum(axis=1), 1.0, atol=1e-15)
+    rows, W = oracle.interpolation_operator(1, p, k, o, 4)
+    a, ext, idx = chk.buffer_grid(o, p, k)
+    for r in range(len(rows)):
+        # o = 0: coarse side is buffer layer 0 (coarse layer 0), layer 1 is the fine-side half
+        w_by_layer = {lay: W[r, idx[:, 0] == lay].sum() for lay in (0, 1)}
+        assert w_by_layer[0] == pytest.approx(2.0 / 3.0, abs=1e-15)
+        assert w_by_layer[1] == pytest.approx(1.0 / 3.0, abs=1e-15)
+    for scheme in (2, 3):
+        with pytest.raises(ValueError):
+            oracle.transfer_operator(0, scheme, p, k, o, 0)
+
+
+def test_restriction_segments_tile_k1():
+    for p, o in product((6, 9), range(6)):
+        seen = []
+        for s in range(9):
+            rows, _ = oracle.restriction_operator(1, p, 1, o, s)
+            seen.extend(rows.tolist())
+        assert len(seen) == len(set(seen)) == p * p
