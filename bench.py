@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--mesh-meshes", type=int, default=3,
                     help="independently seeded 3-level AMR meshes in the per-step leg (0 disables it)")
     ap.add_argument("--mesh-steps", type=int, default=100)
+    ap.add_argument("--patch-faces", type=int, default=6003,
+                    help="fine patches in the fused patch-halo leg, rounded up to a multiple "
+                         "of 9 (0 disables it)")
+    ap.add_argument("--no-reports", action="store_true",
+                    help="skip the convergence and operator-build reports")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -95,6 +100,10 @@ def recorded_traffic(kernel_name, mode="f64"):
         return int(k["read_bytes"] + k["write_bytes"])
     except (OSError, IndexError, KeyError, ValueError):
         return None
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def run_steps(launches, steps, warmup, torch):
@@ -229,6 +238,85 @@ def mesh_leg(args, torch, api, wl):
             "schedule": api.unpack_schedule(best)}
 
 
+def patches_leg(args, torch, api, wl):
+    """The transfer fused with the patch halos (Taylor-3, p=9, k=3, U=59,
+    FP64): fine patches of 9^3 cells, nine per coarse face.  A step restricts
+    every fine patch into its coarse patch's halo and then interpolates every
+    fine halo from its coarse patch.  Unfused: gather the face views into face
+    buffers, apply the face-buffer transfer, scatter the halo halves back.
+    Fused: the transfer reads and writes the patches in place."""
+    import numpy as np
+
+    p, k, U = 9, 3, 59
+    # every coarse face carries all nine of its fine faces
+    b = wl.patch_transitions(-(-args.patch_faces // 9) * 9, p, k, U, seed=wl.SEED_BASE + 6,
+                             device="cuda:0", faces_per_coarse=9)
+    n = b.n
+    groups = -(-n // 9)
+    fe = 2 * k * p * p * U
+    dev = b.coarse.device
+    rop = api.build_transfer_operator(api.FT_RESTRICT, 3, p, k)
+    iop = api.build_transfer_operator(api.FT_INTERPOLATE, 3, p, k)
+    d = (b.orientation, b.subface, b.coarse_offset, b.fine_offset)
+    # unfused: one face buffer per fine face, one per coarse face
+    offs = torch.arange(n, dtype=torch.int64, device=dev) * fe
+    goffs = torch.arange(n, dtype=torch.int64, device=dev) // 9 * fe
+    first = torch.arange(0, n, 9, device=dev)
+    cface = ((b.orientation.to(torch.int64) + 3) % 6).to(torch.int8)
+    gface, gpatch, gbuf = cface[first].contiguous(), b.coarse_offset[first].contiguous(), goffs[first].contiguous()
+    fbuf = torch.zeros(n * fe, dtype=torch.float64, device=dev)
+    cbuf = torch.zeros(groups * fe, dtype=torch.float64, device=dev)
+    uc, uf = b.coarse.clone(), b.fine.clone()
+    fc, ff = b.coarse.clone(), b.fine.clone()
+    BOTH, OUTER = api.FT_HALF_BOTH, api.FT_HALF_OUTER
+    unfused = [
+        ("gather_fine_faces", lambda: api.gather_patch_faces(p, k, b.orientation, b.fine_offset, offs, BOTH, U, uf, fbuf)),
+        ("restrict_faces", lambda: api.restrict_faces(rop, b.orientation, b.subface, goffs, offs, U, fbuf, cbuf)),
+        ("scatter_coarse_halos", lambda: api.scatter_patch_faces(p, k, gface, gpatch, gbuf, OUTER, U, cbuf, uc)),
+        ("gather_coarse_faces", lambda: api.gather_patch_faces(p, k, gface, gpatch, gbuf, BOTH, U, uc, cbuf)),
+        ("interpolate_faces", lambda: api.interpolate_faces(iop, b.orientation, b.subface, goffs, offs, U, cbuf, fbuf)),
+        ("scatter_fine_halos", lambda: api.scatter_patch_faces(p, k, b.orientation, b.fine_offset, offs, OUTER, U, fbuf, uf)),
+    ]
+    fused = [
+        ("restrict_patches", lambda: api.restrict_patches(rop, *d, U, ff, fc)),
+        ("interpolate_patches", lambda: api.interpolate_patches(iop, *d, U, fc, ff)),
+    ]
+    for _, fn in unfused + fused:
+        fn()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(uc, fc) and torch.equal(uf, ff))
+    ms_u, kern_u = run_steps(unfused, args.steps, args.warmup, torch)
+    ms_f, kern_f = run_steps(fused, args.steps, args.warmup, torch)
+    produced = n * (9 * k + k) * (p // 3) ** 2 * U
+    # algorithmic bytes: restriction reads each fine face's stencil cells and
+    # writes its segment; interpolation reads the union of the nine subfaces'
+    # stencil cells of each coarse face and writes every fine halo
+    o_np = b.orientation.cpu().numpy()
+    s_np = b.subface.cpu().numpy()
+    rbytes = algorithmic_bytes(rop, o_np, s_np, U, 8)
+    union = {}
+    rows_per_face = 0
+    for o in range(6):
+        cols_o = set()
+        for s_ in range(9):
+            rows, cols, vals = iop.segment(o, s_)
+            cols_o.update(np.unique(cols[vals != 0]).tolist())
+            rows_per_face = len(np.unique(rows))
+        union[o] = len(cols_o)
+    ibytes = (sum(union[int(o)] for o in o_np[::9]) + n * rows_per_face) * U * 8
+    return {"workload": f"{n} fine patches of 9^3 cells with halo depth 3, nine per coarse face "
+                        f"({groups} coarse patches), Taylor-3, U=59, FP64, restrict then interpolate",
+            "ghost_cell_unknowns_per_step": produced,
+            "unfused_ms_per_step": ms_u, "fused_ms_per_step": ms_f, "speedup": ms_u / ms_f,
+            "fused_value": produced / (ms_f * 1e-3),
+            "fused_equals_unfused_bitwise": same,
+            "kernels_ms": {**{f"unfused/{kk}": round(v, 4) for kk, v in kern_u.items()},
+                           **{f"fused/{kk}": round(v, 4) for kk, v in kern_f.items()}},
+            "fused_GB/s": {"restrict_patches": round(rbytes / (kern_f["restrict_patches"] * 1e-3) / 1e9, 1),
+                           "interpolate_patches": round(ibytes / (kern_f["interpolate_patches"] * 1e-3) / 1e9, 1)},
+            "alg_bytes": {"restrict_patches": rbytes, "interpolate_patches": ibytes}}
+
+
 def cpu_baseline(batch, n_faces, torch):
     """The FP64 oracle on the host, on the first n_faces faces of the same
     batch; operators are built before timing (the paper times repeated calls
@@ -317,6 +405,7 @@ def main():
 
     launches, ops, outs64 = make_launches(torch.float64)
     ms, kern_ms = run_steps(launches, args.steps, args.warmup, torch)
+    progress(f"float64 step: {ms:.3f} ms")
     produced = 3 * n * (9 * k * (p // 3) ** 2 + k * (p // 3) ** 2) * U
     value = produced / (ms * 1e-3)
 
@@ -367,6 +456,7 @@ def main():
                 emax = (g - rr).abs().amax(dim=0) / rr.abs().amax(dim=0)
                 erms = (g - rr).pow(2).mean(dim=0).sqrt() / rr.pow(2).mean(dim=0).sqrt()
                 errs[nm] = {"max_rel": float(emax.max()), "rms_rel": float(erms.max())}
+            progress(f"float32 {label} step: {mms:.3f} ms")
             result["mixed"][label] = {
                 "value": produced / (mms * 1e-3),
                 "ms_per_step": mms,
@@ -378,12 +468,28 @@ def main():
 
     if args.batched_faces > 0:
         result["batched"] = batched_leg(args, torch, api, wl)
+        progress("batched leg done")
 
     if args.mesh_meshes > 0:
         result["mesh"] = mesh_leg(args, torch, api, wl)
+        progress("mesh leg done")
+
+    if args.patch_faces > 0:
+        result["patches"] = patches_leg(args, torch, api, wl)
+        progress("patch leg done")
 
     if args.cpu_faces > 0:
         result["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_faces, n), torch)
+        progress("cpu baseline done")
+
+    if not args.no_reports:
+        from paper_2504_15814_amd import experiments
+
+        del batch  # free the benchmark buffers before the reports allocate theirs
+        torch.cuda.empty_cache()
+        result["convergence"] = experiments.convergence(device=dev)
+        result["operator_build"] = experiments.operator_build(device=dev)
+        progress("reports done")
 
     print(json.dumps(result), flush=True)
 

@@ -42,8 +42,11 @@
  * degree 3), shifted toward the face interior at face edges.  Coinciding
  * centres are copied bit for bit.
  *
- * Supported sizes: p a multiple of 3 with 6 <= p <= 48; k in {2, 3};
- * 1 <= U <= 4096.
+ * Supported sizes: p a multiple of 3 with 6 <= p <= 48; k in {2, 3} for every
+ * scheme and k = 1 (the finite-volume halo of Section 2) for FT_DLINEAR; there
+ * the single fine ghost layer is interpolated between coarse layer 0 and the
+ * coarse face's fine-side layer, and the coarse halo layer is extrapolated
+ * through the fine face's inner layer and its halo layer; 1 <= U <= 4096.
  *
  * ---------------------------------------------------------------------------
  * Ownership, streams and errors
@@ -129,7 +132,8 @@ typedef struct ft_operator ft_operator;
  * out: receives the handle (library-owned; release with
  *      destroy_transfer_operator).
  * Errors: FT_ERR_INVALID (null out, unknown direction / scheme),
- *         FT_ERR_UNSUPPORTED (p, k outside the supported set),
+ *         FT_ERR_UNSUPPORTED (p, k outside the supported set, k = 1 with a
+ *         Taylor scheme),
  *         FT_ERR_NOMEM, FT_ERR_HIP. */
 int build_transfer_operator(int direction, int scheme, int p, int k, int flags,
                             ft_operator** out);
@@ -193,6 +197,94 @@ int transfer_operator_info(const ft_operator* op, int64_t* info, int n_info);
 int transfer_operator_segment(const ft_operator* op, int orientation, int subface,
                               int64_t capacity, int64_t* rows, int64_t* cols, double* vals,
                               int64_t* n_entries);
+
+/* ---------------------------------------------------------------------------
+ * Patches: the transfer fused with the patch halos
+ * ---------------------------------------------------------------------------
+ * Section 2: every patch of p^3 cells carries a halo of depth k on its faces
+ * (not on edges or vertices), refreshed at the start of a time step from the
+ * face-connected neighbours: a plain copy between patches of one level, the
+ * transfer across a resolution transition.  The face buffers above are the 2k
+ * layers around one face; the calls below read and write them in place
+ * inside the patches, so no face buffer has to be assembled and scattered.
+ *
+ * Patch layout: a box of P = p + 2k cells per axis whose interior is
+ * [k, k + p) on every axis; cell (i0, i1, i2) is cell number (i2*P + i1)*P + i0
+ * (axis 0 fastest) and unknown u of it is element cell*U + u.  Edge and vertex
+ * cells of the box exist in storage and are never read or written.
+ *
+ * Patch faces are numbered f = a + 3*upper (f < 3: the face at the lower
+ * boundary along axis a; f >= 3: the upper one).  The face view of face f is
+ * the 2k x p x p box of cells around it: normal cells [0, 2k) (f < 3) or
+ * [p, p + 2k) (f >= 3), tangential cells [k, k + p).  In storage order its
+ * cells are those of a face buffer of that face (layer 0 on the - side).  The
+ * half of the view inside the patch is its inner half, the other its outer
+ * (halo) half.  At a transition face of orientation o the fine patch's face
+ * is f = o and the coarse patch's face is f = (o + 3) mod 6.
+ *
+ * Per-item descriptors live in device memory and are checked by the kernels
+ * against the element counts; an item out of range is skipped and counted
+ * (the transfer in the operator's counter, the copies in *skipped when that
+ * device pointer is not NULL). */
+#define FT_HALF_INNER 1
+#define FT_HALF_OUTER 2
+#define FT_HALF_BOTH 3
+
+/* Interpolate into the halo of each fine patch straight from its coarse
+ * patch: the same arithmetic as interpolate_faces on the face views (the
+ * coarse patch's face view, both halves, is read; the fine patch's outer
+ * half of face o is written).
+ * coarse_offset / fine_offset: element offsets of the coarse and fine
+ * patches (their cell (0, 0, 0)).  Other arguments as for interpolate_faces.
+ * `coarse` and `fine` may be the same array (one pool of patches): a call
+ * reads coarse face views and writes fine halos, which are disjoint as long
+ * as no (fine patch, orientation) pair is listed twice. */
+int interpolate_patches(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                        const int8_t* subface, const int64_t* coarse_offset,
+                        const int64_t* fine_offset, int unknowns, int dtype,
+                        const void* coarse, int64_t coarse_elems, void* fine,
+                        int64_t fine_elems, void* stream);
+
+/* Restrict from each fine patch into the halo of its coarse patch: the same
+ * arithmetic as restrict_faces on the face views (the fine patch's face view
+ * of face o, both halves, is read; in the coarse patch's outer half of face
+ * (o + 3) mod 6 the (p/3)^2 * k cells under the subface are written).
+ * Offsets as for interpolate_patches; `fine` and `coarse` may be one array. */
+int restrict_patches(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                     const int8_t* subface, const int64_t* coarse_offset,
+                     const int64_t* fine_offset, int unknowns, int dtype, const void* fine,
+                     int64_t fine_elems, void* coarse, int64_t coarse_elems, void* stream);
+
+/* Copy the chosen halves (FT_HALF_*) of face view face[i] of the patch at
+ * patch_offset[i] into the face buffer at face_offset[i] (Section 2: the
+ * face data of a patch are its boundary layers and the halo facing them).
+ * p >= 1, 1 <= k <= p, 1 <= U <= 4096; dtype selects the element size only
+ * (FT_F64: 8 bytes, the float32 modes: 4 bytes; values are copied bit for
+ * bit).  face: device int8[n], 0..5; offsets: device int64[n].  patches and
+ * faces must not overlap.  skipped: device int, or NULL. */
+int gather_patch_faces(int p, int k, int64_t n, const int8_t* face, const int64_t* patch_offset,
+                       const int64_t* face_offset, int halves, int unknowns, int dtype,
+                       const void* patches, int64_t patch_elems, void* faces,
+                       int64_t face_elems, int* skipped, void* stream);
+
+/* The reverse of gather_patch_faces: the chosen halves of each face buffer
+ * are written into face view face[i] of its patch. */
+int scatter_patch_faces(int p, int k, int64_t n, const int8_t* face, const int64_t* patch_offset,
+                        const int64_t* face_offset, int halves, int unknowns, int dtype,
+                        const void* faces, int64_t face_elems, void* patches,
+                        int64_t patch_elems, int* skipped, void* stream);
+
+/* Same-level halo exchange (Section 2: where both neighbours have one
+ * resolution the halo is a copy).  Pair i: the patch at lower_offset[i]
+ * touches the patch at upper_offset[i] across its upper face along axis[i]
+ * (device int8, 0..2).  The lower patch's upper halo receives the upper
+ * patch's first k interior layers, and the upper patch's lower halo the lower
+ * patch's last k interior layers.  Both patches live in `patches`; a call
+ * reads interiors and writes halos, so pairs may share patches, but each halo
+ * (patch, face) must be written by at most one pair. */
+int copy_patch_halos(int p, int k, int64_t n_pairs, const int8_t* axis,
+                     const int64_t* lower_offset, const int64_t* upper_offset, int unknowns,
+                     int dtype, void* patches, int64_t patch_elems, int* skipped, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Plans: uneven mixes in one launch

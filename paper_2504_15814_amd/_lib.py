@@ -46,6 +46,31 @@ SIGNATURES = {
         [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
          c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64, c_void_p],
     ),
+    "interpolate_patches": (
+        ctypes.c_int,
+        [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+         c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64, c_void_p],
+    ),
+    "restrict_patches": (
+        ctypes.c_int,
+        [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+         c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64, c_void_p],
+    ),
+    "gather_patch_faces": (
+        ctypes.c_int,
+        [ctypes.c_int, ctypes.c_int, ctypes.c_int64, c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+         ctypes.c_int, c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64, c_void_p, c_void_p],
+    ),
+    "scatter_patch_faces": (
+        ctypes.c_int,
+        [ctypes.c_int, ctypes.c_int, ctypes.c_int64, c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+         ctypes.c_int, c_void_p, ctypes.c_int64, c_void_p, ctypes.c_int64, c_void_p, c_void_p],
+    ),
+    "copy_patch_halos": (
+        ctypes.c_int,
+        [ctypes.c_int, ctypes.c_int, ctypes.c_int64, c_void_p, c_void_p, c_void_p, ctypes.c_int, ctypes.c_int,
+         c_void_p, ctypes.c_int64, c_void_p, c_void_p],
+    ),
     "transfer_operator_info": (ctypes.c_int, [c_void_p, c_int64_p, ctypes.c_int]),
     "transfer_operator_segment": (
         ctypes.c_int,

@@ -17,6 +17,7 @@ FT_INTERPOLATE, FT_RESTRICT = 0, 1
 FT_DLINEAR, FT_TAYLOR2, FT_TAYLOR3 = 1, 2, 3
 FT_F64, FT_F32, FT_F32_BF16X3, FT_F32_BF16X6 = 0, 1, 2, 3
 FT_BUILD_HOST_ONLY = 1
+FT_HALF_INNER, FT_HALF_OUTER, FT_HALF_BOTH = 1, 2, 3
 
 _DTYPES = {torch.float64: FT_F64, torch.float32: FT_F32}
 
@@ -157,6 +158,96 @@ def restrict_faces(op, orientation, subface, coarse_offset, fine_offset, unknown
             unknowns, dt, _ptr(fine), fine.numel(), _ptr(coarse), coarse.numel(),
             _stream_ptr(stream)),
         "restrict_faces",
+    )
+
+
+def interpolate_patches(op, orientation, subface, coarse_offset, fine_offset, unknowns, coarse, fine,
+                        stream=None, mode=None):
+    """Fill each fine patch's halo across its transition face straight from
+    the coarse patch (offsets are patch offsets; coarse and fine may be the
+    same tensor)."""
+    n = _descriptors(orientation, subface, coarse_offset, fine_offset)
+    dt = _mode(coarse, fine, mode)
+    _check(
+        _lib.load().interpolate_patches(
+            op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
+            unknowns, dt, _ptr(coarse), coarse.numel(), _ptr(fine), fine.numel(),
+            _stream_ptr(stream)),
+        "interpolate_patches",
+    )
+
+
+def restrict_patches(op, orientation, subface, coarse_offset, fine_offset, unknowns, fine, coarse,
+                     stream=None, mode=None):
+    """Fill, in each coarse patch's halo, the segment under each fine patch."""
+    n = _descriptors(orientation, subface, coarse_offset, fine_offset)
+    dt = _mode(fine, coarse, mode)
+    _check(
+        _lib.load().restrict_patches(
+            op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
+            unknowns, dt, _ptr(fine), fine.numel(), _ptr(coarse), coarse.numel(),
+            _stream_ptr(stream)),
+        "restrict_patches",
+    )
+
+
+def _copy_descriptors(sel, off_a, off_b):
+    for name, t, dt in (("selector", sel, torch.int8), ("offset", off_a, torch.int64),
+                        ("offset", off_b, torch.int64)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {dt} tensor")
+    n = sel.numel()
+    if not (off_a.numel() == off_b.numel() == n):
+        raise ValueError("descriptor arrays differ in length")
+    return n
+
+
+def _elem_mode(*tensors):
+    dts = {t.dtype for t in tensors}
+    if len(dts) != 1 or tensors[0].dtype not in _DTYPES:
+        raise TypeError("buffers must share dtype float64 or float32")
+    return _DTYPES[tensors[0].dtype]
+
+
+def gather_patch_faces(p, k, face, patch_offset, face_offset, halves, unknowns, patches, faces,
+                       skipped=None, stream=None):
+    """Copy the chosen halves of face view face[i] of each patch into its
+    face buffer.  skipped: optional int32 device tensor counting bad items."""
+    n = _copy_descriptors(face, patch_offset, face_offset)
+    _check(
+        _lib.load().gather_patch_faces(
+            p, k, n, _ptr(face), _ptr(patch_offset), _ptr(face_offset), halves, unknowns,
+            _elem_mode(patches, faces), _ptr(patches), patches.numel(), _ptr(faces), faces.numel(),
+            _ptr(skipped), _stream_ptr(stream)),
+        "gather_patch_faces",
+    )
+
+
+def scatter_patch_faces(p, k, face, patch_offset, face_offset, halves, unknowns, faces, patches,
+                        skipped=None, stream=None):
+    """Write the chosen halves of each face buffer into face view face[i] of
+    its patch."""
+    n = _copy_descriptors(face, patch_offset, face_offset)
+    _check(
+        _lib.load().scatter_patch_faces(
+            p, k, n, _ptr(face), _ptr(patch_offset), _ptr(face_offset), halves, unknowns,
+            _elem_mode(patches, faces), _ptr(faces), faces.numel(), _ptr(patches), patches.numel(),
+            _ptr(skipped), _stream_ptr(stream)),
+        "scatter_patch_faces",
+    )
+
+
+def copy_patch_halos(p, k, axis, lower_offset, upper_offset, unknowns, patches, skipped=None,
+                     stream=None):
+    """Same-level halo exchange across the upper face (along axis[i]) of the
+    patch at lower_offset[i]."""
+    n = _copy_descriptors(axis, lower_offset, upper_offset)
+    _check(
+        _lib.load().copy_patch_halos(
+            p, k, n, _ptr(axis), _ptr(lower_offset), _ptr(upper_offset), unknowns,
+            _elem_mode(patches), _ptr(patches), patches.numel(), _ptr(skipped),
+            _stream_ptr(stream)),
+        "copy_patch_halos",
     )
 
 

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-std=c++17", "-fPIC", "-O3", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
-DEVICE_SOURCES = ["ft_kernels.hip", "ft_mfma.hip", "ft_plan.hip"]
+DEVICE_SOURCES = ["ft_kernels.hip", "ft_mfma.hip", "ft_plan.hip", "ft_patch.hip"]
 HOST_SOURCES = ["ft_builder.cpp", "ft_api.cpp"]
 
 

@@ -161,7 +161,8 @@ int upload(ft_operator* op) {
 
 int check_apply(const ft_operator* op, int direction, int64_t n_faces, const void* orientation,
                 const void* subface, const void* so, const void* dof, int unknowns, int dtype,
-                const void* src, int64_t src_elems, const void* dst, int64_t dst_elems) {
+                const void* src, int64_t src_elems, const void* dst, int64_t dst_elems,
+                bool patches = false) {
   if (!op) return fail(FT_ERR_INVALID, "operator is NULL");
   if (op->direction != direction)
     return fail(FT_ERR_INVALID, direction == FT_INTERPOLATE
@@ -178,11 +179,35 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
   if (n_faces == 0) return FT_OK;
   if (!orientation || !subface || !so || !dof || !src || !dst)
     return fail(FT_ERR_INVALID, "NULL descriptor or buffer pointer");
-  if (src == dst) return fail(FT_ERR_INVALID, "source and destination alias");
+  // Face buffers: a face's source and destination are one cell box, so one
+  // array for both would overwrite what is read.  Patches: a call reads face
+  // views and writes halos of other faces, so one pool may hold both.
+  if (src == dst && !patches) return fail(FT_ERR_INVALID, "source and destination alias");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != op->device) return fail(FT_ERR_INVALID, "operator belongs to another device");
+  return FT_OK;
+}
+
+// Host checks of the patch / face-buffer copies.  dst == nullptr: the
+// same-level halo exchange, which reads and writes one array.
+int check_copy(int p, int k, int64_t n, const void* sel, const void* off_a, const void* off_b,
+               int halves, int unknowns, int dtype, const void* src, int64_t src_elems,
+               const void* dst, int64_t dst_elems) {
+  if (p < 1 || p > 1024) return fail(FT_ERR_UNSUPPORTED, "p must be in 1..1024");
+  if (k < 1 || k > p) return fail(FT_ERR_UNSUPPORTED, "k must be in 1..p");
+  const int64_t P = p + 2 * k;
+  if (P * P * P > ((int64_t)1 << 31) - 1) return fail(FT_ERR_UNSUPPORTED, "patch too large");
+  if (n < 0) return fail(FT_ERR_INVALID, "negative item count");
+  if (unknowns < 1 || unknowns > 4096) return fail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
+  if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return fail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (halves < FT_HALF_INNER || halves > FT_HALF_BOTH)
+    return fail(FT_ERR_INVALID, "halves must be FT_HALF_INNER, FT_HALF_OUTER or FT_HALF_BOTH");
+  if (src_elems < 0 || dst_elems < 0) return fail(FT_ERR_INVALID, "negative buffer size");
+  if (n == 0) return FT_OK;
+  if (!sel || !off_a || !off_b || !src) return fail(FT_ERR_INVALID, "NULL descriptor or buffer");
+  if (dst == src) return fail(FT_ERR_INVALID, "source and destination alias");
   return FT_OK;
 }
 
@@ -202,7 +227,9 @@ int build_transfer_operator(int direction, int scheme, int p, int k, int flags,
     return fail(FT_ERR_INVALID, "scheme must be FT_DLINEAR, FT_TAYLOR2 or FT_TAYLOR3");
   if (p < 6 || p > ft::kMaxP || p % 3 != 0)
     return fail(FT_ERR_UNSUPPORTED, "p must be a multiple of 3 in [6, 48]");
-  if (k != 2 && k != 3) return fail(FT_ERR_UNSUPPORTED, "k must be 2 or 3");
+  if (k < 1 || k > 3) return fail(FT_ERR_UNSUPPORTED, "k must be 1, 2 or 3");
+  if (k == 1 && scheme != FT_DLINEAR)
+    return fail(FT_ERR_UNSUPPORTED, "k = 1 is supported by FT_DLINEAR only");
   if (flags & ~FT_BUILD_HOST_ONLY) return fail(FT_ERR_INVALID, "unknown flags");
   ft_operator* op = new (std::nothrow) ft_operator();
   if (!op) return fail(FT_ERR_NOMEM, "host allocation failed");
@@ -272,6 +299,84 @@ int restrict_faces(const ft_operator* op, int64_t n_faces, const int8_t* orienta
                     fine, fine_elems, coarse, coarse_elems, op->d_errors};
   hipError_t e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "restrict_faces launch");
+  return ok();
+}
+
+int interpolate_patches(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                        const int8_t* subface, const int64_t* coarse_offset,
+                        const int64_t* fine_offset, int unknowns, int dtype, const void* coarse,
+                        int64_t coarse_elems, void* fine, int64_t fine_elems, void* stream) {
+  int rc = check_apply(op, FT_INTERPOLATE, n_faces, orientation, subface, coarse_offset,
+                       fine_offset, unknowns, dtype, coarse, coarse_elems, fine, fine_elems, true);
+  if (rc != FT_OK || n_faces == 0) return rc == FT_OK ? ok() : rc;
+  ft::LaunchArgs la{n_faces, orientation, subface, coarse_offset, fine_offset, unknowns, dtype,
+                    coarse, coarse_elems, fine, fine_elems, op->d_errors, ft::kPatches};
+  hipError_t e;
+  if (dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6)
+    e = ft::launch_interp_mfma(op, la, ft::LaunchConfig(), dtype == FT_F32_BF16X6 ? 6 : 3,
+                               (hipStream_t)stream);
+  else
+    e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "interpolate_patches launch");
+  return ok();
+}
+
+int restrict_patches(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
+                     const int8_t* subface, const int64_t* coarse_offset,
+                     const int64_t* fine_offset, int unknowns, int dtype, const void* fine,
+                     int64_t fine_elems, void* coarse, int64_t coarse_elems, void* stream) {
+  int rc = check_apply(op, FT_RESTRICT, n_faces, orientation, subface, fine_offset,
+                       coarse_offset, unknowns, dtype, fine, fine_elems, coarse, coarse_elems,
+                       true);
+  if (rc != FT_OK || n_faces == 0) return rc == FT_OK ? ok() : rc;
+  ft::LaunchArgs la{n_faces, orientation, subface, fine_offset, coarse_offset, unknowns, dtype,
+                    fine, fine_elems, coarse, coarse_elems, op->d_errors, ft::kPatches};
+  hipError_t e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "restrict_patches launch");
+  return ok();
+}
+
+int gather_patch_faces(int p, int k, int64_t n, const int8_t* face, const int64_t* patch_offset,
+                       const int64_t* face_offset, int halves, int unknowns, int dtype,
+                       const void* patches, int64_t patch_elems, void* faces, int64_t face_elems,
+                       int* skipped, void* stream) {
+  const int rc = check_copy(p, k, n, face, patch_offset, face_offset, halves, unknowns, dtype,
+                            patches, patch_elems, faces, face_elems);
+  if (rc != FT_OK || n == 0) return rc == FT_OK ? ok() : rc;
+  ft::FaceCopyArgs c{ft::kGatherFaces, p, k, halves, n, face, patch_offset, face_offset,
+                     unknowns, dtype == FT_F64 ? 8 : 4, patches, patch_elems, faces,
+                     face_elems, skipped};
+  const hipError_t e = ft::launch_face_copy(c, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gather_patch_faces launch");
+  return ok();
+}
+
+int scatter_patch_faces(int p, int k, int64_t n, const int8_t* face, const int64_t* patch_offset,
+                        const int64_t* face_offset, int halves, int unknowns, int dtype,
+                        const void* faces, int64_t face_elems, void* patches,
+                        int64_t patch_elems, int* skipped, void* stream) {
+  const int rc = check_copy(p, k, n, face, patch_offset, face_offset, halves, unknowns, dtype,
+                            faces, face_elems, patches, patch_elems);
+  if (rc != FT_OK || n == 0) return rc == FT_OK ? ok() : rc;
+  ft::FaceCopyArgs c{ft::kScatterFaces, p, k, halves, n, face, patch_offset, face_offset,
+                     unknowns, dtype == FT_F64 ? 8 : 4, faces, face_elems, patches,
+                     patch_elems, skipped};
+  const hipError_t e = ft::launch_face_copy(c, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "scatter_patch_faces launch");
+  return ok();
+}
+
+int copy_patch_halos(int p, int k, int64_t n_pairs, const int8_t* axis,
+                     const int64_t* lower_offset, const int64_t* upper_offset, int unknowns,
+                     int dtype, void* patches, int64_t patch_elems, int* skipped, void* stream) {
+  const int rc = check_copy(p, k, n_pairs, axis, lower_offset, upper_offset, FT_HALF_BOTH,
+                            unknowns, dtype, patches, patch_elems, nullptr, patch_elems);
+  if (rc != FT_OK || n_pairs == 0) return rc == FT_OK ? ok() : rc;
+  ft::FaceCopyArgs c{ft::kHaloPairs, p, k, FT_HALF_BOTH, n_pairs, axis, lower_offset,
+                     upper_offset, unknowns, dtype == FT_F64 ? 8 : 4, patches, patch_elems,
+                     patches, patch_elems, skipped};
+  const hipError_t e = ft::launch_face_copy(c, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "copy_patch_halos launch");
   return ok();
 }
 
@@ -370,6 +475,6 @@ int transfer_operator_errors(const ft_operator* op, int64_t* n_skipped, int rese
 
 const char* transfer_last_error(void) { return g_last_error.c_str(); }
 
-int transfer_version(void) { return 100; }
+int transfer_version(void) { return 200; }
 
 }  // extern "C"

@@ -260,7 +260,9 @@ std::string build_tables(ft_operator* op) {
   op->copy_row = -1;
   op->copy_n = 0;
   if (op->direction == 0) {
-    op->copy_row = 13;  // (g, tb, tc) = (1, 1, 1): the coarse centre itself
+    // (g, tb, tc) = (1, 1, 1): the coarse centre itself; with k = 1 no fine
+    // ghost centre coincides with a coarse one
+    op->copy_row = k >= 2 ? 13 : -1;
     op->copy_n = 0;
   } else if (op->scheme != FT_DLINEAR) {
     op->copy_row = 0;  // layer 0 coincides with fine layer 1 (k >= 2)

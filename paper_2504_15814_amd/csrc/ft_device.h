@@ -50,7 +50,7 @@ __device__ __forceinline__ const FT_CONST P* cptr(const P* p) {
 // 0 of every block) or -1.  T storage, A accumulator, W weight type.
 template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W>
 __device__ __forceinline__ void apply_item(
-    const DevOp* __restrict__ op_, const int face, const int e,
+    const DevOp* __restrict__ op_, const int face, const int e, const int layout,
     const int8_t* __restrict__ orientation_, const int8_t* __restrict__ subface_,
     const int64_t* __restrict__ src_offset_, const int64_t* __restrict__ dst_offset_, const int U,
     const T* __restrict__ src, const int64_t src_elems, T* __restrict__ dst,
@@ -69,32 +69,37 @@ __device__ __forceinline__ void apply_item(
 
   const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
   const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
-  const int64_t face_elems = (int64_t)(2 * k * p * p) * U;
+  // Elements one item may touch: a face buffer, or a whole patch box.
+  const int P = p + 2 * k;
+  const int64_t item_elems =
+      (layout == kFaceBuffers ? (int64_t)(2 * k * p * p) : (int64_t)P * P * P) * U;
   const int64_t so = src_offset[face];
   const int64_t dof = dst_offset[face];
   const bool bad = o < 0 || o > 5 || s < 0 || s > 8 || so < 0 || dof < 0 ||
-                   so > src_elems - face_elems || dof > dst_elems - face_elems;
+                   so > src_elems - item_elems || dof > dst_elems - item_elems;
   if (bad) {
     if (e == 0 && lane == 0) atomicAdd(errors, 1);
     return;
   }
-  const FaceStrides st = face_strides(o % 3, p, k);
+  FaceView sv, dv;
+  transfer_views(DIR, layout, o, p, k, &sv, &dv);
   int nbase, nsign;
   normal_map(DIR, o, k, &nbase, &nsign);
   const int sb = s % 3, sc = s / 3;
 
-  // Anchor column in the source buffer and the block that serves it.
+  // Anchor column in the source face and the block that serves it.
   const int anc_b = DIR == 0 ? sb * E + eb : 3 * eb + 1;
   const int anc_c = DIR == 0 ? sc * E + ec : 3 * ec + 1;
   const int cls = axis_class(anc_b, p) * kAxisClasses + axis_class(anc_c, p);
   const int width = op->width[cls];
   const int start = op->start[cls];
-  const int anchor_cell = anc_b * st.sb + anc_c * st.sc + nbase * st.sa;
-  const int nstride = nsign * st.sa;
+  const int anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
+  const int nstride = nsign * sv.sa;
   // First destination cell of this anchor and the strides of its rows.
   const int dst_b = DIR == 0 ? 3 * eb : sb * E + eb;
   const int dst_c = DIR == 0 ? 3 * ec : sc * E + ec;
-  const int dst_cell0 = nbase * st.sa + dst_b * st.sb + dst_c * st.sc;
+  const int dst_cell0 = dv.base + nbase * dv.sa + dst_b * dv.sb + dst_c * dv.sc;
+  const int dstride = nsign * dv.sa;
 
   const T* __restrict__ sp = src + so;
   T* __restrict__ dp = dst + dof;
@@ -116,7 +121,7 @@ __device__ __forceinline__ void apply_item(
       for (int j = 0; j < kGroup; ++j) {
         int n, db, dc;
         unpack_point(pts[q + j], &n, &db, &dc);
-        const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+        const int cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
         x[j] = A(sp[(int64_t)cell * U + uu]);
       }
       if (COPY >= 0 && q == 0) copy_val = x[0];
@@ -131,7 +136,7 @@ __device__ __forceinline__ void apply_item(
     for (; q < width; ++q) {
       int n, db, dc;
       unpack_point(pts[q], &n, &db, &dc);
-      const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+      const int cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
       const A x = A(sp[(int64_t)cell * U + uu]);
       if (COPY >= 0 && q == 0) copy_val = x;
       const FT_CONST W* w = wts + q * R;
@@ -145,9 +150,9 @@ __device__ __forceinline__ void apply_item(
       int dcell;
       if (DIR == 0) {
         const int g = r / 9, tb = (r / 3) % 3, tc = r % 3;
-        dcell = dst_cell0 + g * nstride + tb * st.sb + tc * st.sc;
+        dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
       } else {
-        dcell = dst_cell0 + r * nstride;
+        dcell = dst_cell0 + r * dstride;
       }
       // Streaming (non-temporal) stores: the written halo is not re-read by
       // this launch, and keeping it out of L2 preserves the source
@@ -161,8 +166,8 @@ __device__ __forceinline__ void apply_item(
 // tile_all: the block's LDS transpose tiles, one per wave (wave_slot < 4).
 template <int R, int EC, int TERMS>
 __device__ __forceinline__ void mfma_item(
-    const DevOp* __restrict__ op_, const int face, const int e, const int wave_slot,
-    float (*tile_all)[32][65], const int8_t* __restrict__ orientation_,
+    const DevOp* __restrict__ op_, const int face, const int e, const int layout,
+    const int wave_slot, float (*tile_all)[32][65], const int8_t* __restrict__ orientation_,
     const int8_t* __restrict__ subface_, const int64_t* __restrict__ src_offset_,
     const int64_t* __restrict__ dst_offset_, const int U, const float* __restrict__ src,
     const int64_t src_elems, float* __restrict__ dst, const int64_t dst_elems,
@@ -172,7 +177,9 @@ __device__ __forceinline__ void mfma_item(
   const FT_CONST int8_t* subface = cptr(subface_);
   const FT_CONST int64_t* src_offset = cptr(src_offset_);
   const FT_CONST int64_t* dst_offset = cptr(dst_offset_);
-  constexpr int COPY = 13;  // (g, tb, tc) = (1, 1, 1): the coarse centre itself
+  // Row (g, tb, tc) = (1, 1, 1) is the coarse centre itself when k >= 2 (R >= 18);
+  // with k = 1 (R = 9) no row is a copy.
+  constexpr int COPY = R >= 18 ? 13 : -1;
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, col = lane & 31;
   const int E = EC > 0 ? EC : op->E;
@@ -181,35 +188,39 @@ __device__ __forceinline__ void mfma_item(
 
   const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
   const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
-  const int64_t face_elems = (int64_t)(2 * k * p * p) * U;
+  const int P = p + 2 * k;
+  const int64_t item_elems =
+      (layout == kFaceBuffers ? (int64_t)(2 * k * p * p) : (int64_t)P * P * P) * U;
   const int64_t so = src_offset[face];
   const int64_t dof = dst_offset[face];
   const bool bad = o < 0 || o > 5 || s < 0 || s > 8 || so < 0 || dof < 0 ||
-                   so > src_elems - face_elems || dof > dst_elems - face_elems;
+                   so > src_elems - item_elems || dof > dst_elems - item_elems;
   if (bad) {
     if (e == 0 && lane == 0) atomicAdd(errors, 1);
     return;
   }
-  const FaceStrides st = face_strides(o % 3, p, k);
+  FaceView sv, dv;
+  transfer_views(0, layout, o, p, k, &sv, &dv);
   int nbase, nsign;
   normal_map(0, o, k, &nbase, &nsign);
-  const int nstride = nsign * st.sa;
+  const int nstride = nsign * sv.sa;
+  const int dstride = nsign * dv.sa;
   const int sb = s % 3, sc = s / 3;
   const int anc_b = sb * E + eb, anc_c = sc * E + ec;
   const int cls = axis_class(anc_b, p) * kAxisClasses + axis_class(anc_c, p);
   const int width = op->width[cls];
   const int start = op->start[cls];
   const int nsteps = (width + kMfmaK - 1) / kMfmaK;
-  const int anchor_cell = anc_b * st.sb + anc_c * st.sc + nbase * st.sa;
-  const int dst_cell0 = nbase * st.sa + 3 * eb * st.sb + 3 * ec * st.sc;
+  const int anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
+  const int dst_cell0 = dv.base + nbase * dv.sa + 3 * eb * dv.sb + 3 * ec * dv.sc;
 
   const FT_CONST bf16x8* wt = cptr(reinterpret_cast<const bf16x8*>(op->wbf16));
   const FT_CONST int* pts = cptr(op->stencil) + start;
-  int copy_cell;
-  {
+  int copy_cell = anchor_cell;
+  if (COPY >= 0) {
     int n, db, dc;
     unpack_point(pts[0], &n, &db, &dc);  // the copy source is entry 0
-    copy_cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+    copy_cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
   }
 
   const float* __restrict__ sp = src + so;
@@ -240,7 +251,7 @@ __device__ __forceinline__ void mfma_item(
         if (q < width) {
           int n, db, dc;
           unpack_point(pts[q], &n, &db, &dc);
-          const int cell = anchor_cell + n * nstride + db * st.sb + dc * st.sc;
+          const int cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
           x[j] = sp[(int64_t)cell * U + uu];
         }
       }
@@ -297,11 +308,11 @@ __device__ __forceinline__ void mfma_item(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int u = u0 + lane;
     if (u < U) {
-      const float xc = sp[(int64_t)copy_cell * U + u];
+      const float xc = COPY >= 0 ? sp[(int64_t)copy_cell * U + u] : 0.0f;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         const int g = m / 9, tb = (m / 3) % 3, tc = m % 3;
-        const int dcell = dst_cell0 + g * nstride + tb * st.sb + tc * st.sc;
+        const int dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
         __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
       }
     }

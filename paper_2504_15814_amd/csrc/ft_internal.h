@@ -52,6 +52,51 @@ __host__ __device__ inline FaceStrides face_strides(int a, int p, int k) {
   return s;
 }
 
+// Where the 2k x p x p cells of one face live: cell (ia, ib, ic) of the face
+// (normal index ia in face-buffer numbering, tangential ib, ic) is cell
+// base + ia * sa + ib * sb + ic * sc of the array.
+struct FaceView {
+  int sa, sb, sc, base;
+};
+// The face buffer itself.
+__host__ __device__ inline FaceView buffer_view(int a, int p, int k) {
+  const FaceStrides s = face_strides(a, p, k);
+  return FaceView{s.sa, s.sb, s.sc, 0};
+}
+// Face `face` (a + 3 * upper) of a patch box of (p + 2k)^3 cells, interior
+// [k, k + p) per axis, axis 0 fastest: normal layers [0, 2k) for a lower face,
+// [p, p + 2k) for an upper face, tangential cells [k, k + p).
+__host__ __device__ inline FaceView patch_view(int face, int p, int k) {
+  const int P = p + 2 * k;
+  const int a = face % 3;
+  const int b = a == 0 ? 1 : 0;
+  const int c = a == 2 ? 1 : 2;
+  const int S[3] = {1, P, P * P};
+  FaceView v;
+  v.sa = S[a];
+  v.sb = S[b];
+  v.sc = S[c];
+  v.base = (face >= 3 ? p : 0) * v.sa + k * v.sb + k * v.sc;
+  return v;
+}
+
+// Layout of the arrays a transfer call reads and writes.
+enum Layout { kFaceBuffers = 0, kPatches = 1 };
+
+// Source and destination views of one hanging face of orientation o.  With
+// patches the fine patch's face is o and the coarse patch's face (o + 3) % 6.
+__host__ __device__ inline void transfer_views(int direction, int layout, int o, int p, int k,
+                                               FaceView* src, FaceView* dst) {
+  if (layout == kFaceBuffers) {
+    *src = *dst = buffer_view(o % 3, p, k);
+    return;
+  }
+  const FaceView coarse = patch_view((o + 3) % 6, p, k);
+  const FaceView fine = patch_view(o, p, k);
+  *src = direction == 0 ? coarse : fine;
+  *dst = direction == 0 ? fine : coarse;
+}
+
 // Buffer index along the normal of reference coordinate n: base + sign * n.
 // Interpolation: n counts into the coarse side, which is the - side (buffer
 // indices k-1, k-2, ...) when the fine patch lies on the + side (o < 3).

@@ -20,6 +20,7 @@ struct LaunchArgs {
   void* dst;
   int64_t dst_elems;
   int* errors;
+  int layout = kFaceBuffers;  // kFaceBuffers or kPatches
 };
 
 // Tunable launch shape (schedules never change the per-output summation
@@ -35,5 +36,26 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
 // Float32 interpolation on the matrix cores with 3 or 6 split-bfloat16 terms.
 hipError_t launch_interp_mfma(const ft_operator* op, const LaunchArgs& la,
                               const LaunchConfig& cfg, int terms, hipStream_t stream);
+
+// Copies of face views between patches and face buffers, and same-level halo
+// pairs (see ft_patch.hip).
+enum FaceCopyMode { kGatherFaces = 0, kScatterFaces = 1, kHaloPairs = 2 };
+struct FaceCopyArgs {
+  int mode;
+  int p, k;
+  int halves;  // FT_HALF_* (gather / scatter)
+  int64_t n_items;
+  const int8_t* sel;  // patch face (gather / scatter) or axis (halo pairs)
+  const int64_t* off_a;
+  const int64_t* off_b;
+  int U;
+  int elem_size;  // 4 or 8 bytes
+  const void* src;
+  int64_t src_elems;
+  void* dst;
+  int64_t dst_elems;
+  int* errors;  // may be null
+};
+hipError_t launch_face_copy(const FaceCopyArgs& c, hipStream_t stream);
 
 }  // namespace ft

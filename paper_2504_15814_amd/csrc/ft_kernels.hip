@@ -17,6 +17,7 @@ struct Geometry {
   int anchors;  // expansion anchors per face, E * E
   int waves_per_block;
   int xcd_remap;  // 1: consecutive logical blocks land on one XCD
+  int layout;     // kFaceBuffers or kPatches
 };
 
 __device__ inline int64_t logical_block(int xcd_remap) {
@@ -46,8 +47,8 @@ __global__ __launch_bounds__(256) void apply_kernel(
   const int item = (int)logical_block(geo.xcd_remap) * geo.waves_per_block + wave;
   const int face = item / anchors;
   if (face >= geo.n_faces) return;
-  apply_item<DIR, R, EC, COPY, T, A, W>(op, face, item - face * anchors, orientation, subface,
-                                        src_offset, dst_offset, U, src, src_elems, dst,
+  apply_item<DIR, R, EC, COPY, T, A, W>(op, face, item - face * anchors, geo.layout, orientation,
+                                        subface, src_offset, dst_offset, U, src, src_elems, dst,
                                         dst_elems, weights, errors);
 }
 
@@ -94,9 +95,12 @@ static hipError_t launch_typed(const ft_operator* op, const Geometry& g, const L
   const IA* iw;
   if constexpr (sizeof(IA) == 8) iw = d.w64; else iw = d.w32;
   if (op->direction == FT_INTERPOLATE) {
+    if (op->k == 1) return launch_e<0, 9, -1, T, IA, IA>(op, g, la, iw, stream);
     if (op->k == 2) return launch_e<0, 18, 13, T, IA, IA>(op, g, la, iw, stream);
     return launch_e<0, 27, 13, T, IA, IA>(op, g, la, iw, stream);
   }
+  // k = 1: d-linear only, no injection row
+  if (op->k == 1) return launch_e<1, 1, -1, T, double, double>(op, g, la, d.w64, stream);
   const bool inject = op->copy_row == 0;
   if (op->k == 2)
     return inject ? launch_e<1, 2, 0, T, double, double>(op, g, la, d.w64, stream)
@@ -113,6 +117,7 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
   g.anchors = op->E * op->E;
   g.waves_per_block = cfg.waves_per_block;
   g.xcd_remap = cfg.xcd_remap;
+  g.layout = la.layout;
   if (la.dtype == FT_F64) return launch_typed<double, double>(op, g, la, stream);
   // FT_F32 and (for restriction) the split-bfloat16 modes: float32 storage.
   return launch_typed<float, float>(op, g, la, stream);

@@ -17,7 +17,7 @@ __global__ __launch_bounds__(256) void interp_mfma_kernel(
     const int8_t* __restrict__ orientation, const int8_t* __restrict__ subface,
     const int64_t* __restrict__ src_offset, const int64_t* __restrict__ dst_offset, const int U,
     const float* __restrict__ src, const int64_t src_elems, float* __restrict__ dst,
-    const int64_t dst_elems, int* __restrict__ errors) {
+    const int64_t dst_elems, int* __restrict__ errors, const int layout) {
   __shared__ float tile_all[4][32][65];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int E = EC > 0 ? EC : op->E;
@@ -25,8 +25,9 @@ __global__ __launch_bounds__(256) void interp_mfma_kernel(
   const int item = (int)blockIdx.x * waves_per_block + wave;
   const int face = item / anchors;
   if (face >= n_faces) return;
-  mfma_item<R, EC, TERMS>(op, face, item - face * anchors, wave, tile_all, orientation, subface,
-                          src_offset, dst_offset, U, src, src_elems, dst, dst_elems, errors);
+  mfma_item<R, EC, TERMS>(op, face, item - face * anchors, layout, wave, tile_all, orientation,
+                          subface, src_offset, dst_offset, U, src, src_elems, dst, dst_elems,
+                          errors);
 }
 
 template <int R, int EC, int TERMS>
@@ -42,7 +43,7 @@ static hipError_t launch_mfma_one(const ft_operator* op, const LaunchArgs& la,
                        cfg.waves_per_block, la.orientation + f0, la.subface + f0,
                        la.src_offset + f0, la.dst_offset + f0, la.U,
                        static_cast<const float*>(la.src), la.src_elems,
-                       static_cast<float*>(la.dst), la.dst_elems, la.errors);
+                       static_cast<float*>(la.dst), la.dst_elems, la.errors, la.layout);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -63,6 +64,9 @@ static hipError_t launch_mfma_e(const ft_operator* op, const LaunchArgs& la,
 hipError_t launch_interp_mfma(const ft_operator* op, const LaunchArgs& la,
                               const LaunchConfig& cfg, int terms, hipStream_t stream) {
   if (cfg.waves_per_block < 1 || cfg.waves_per_block > 4) return hipErrorInvalidValue;
+  if (op->k == 1)
+    return terms == 6 ? launch_mfma_e<9, 6>(op, la, cfg, stream)
+                      : launch_mfma_e<9, 3>(op, la, cfg, stream);
   if (op->k == 2)
     return terms == 6 ? launch_mfma_e<18, 6>(op, la, cfg, stream)
                       : launch_mfma_e<18, 3>(op, la, cfg, stream);

@@ -21,7 +21,16 @@
 
 namespace ft {
 
-enum PlanKind { kInterp18, kInterp27, kRestrict2Inject, kRestrict2Plain, kRestrict3Inject, kRestrict3Plain };
+enum PlanKind {
+  kInterp18,
+  kInterp27,
+  kRestrict2Inject,
+  kRestrict2Plain,
+  kRestrict3Inject,
+  kRestrict3Plain,
+  kInterp9,        // k = 1
+  kRestrict1Plain  // k = 1
+};
 
 struct PlanSeg {
   const DevOp* op;
@@ -46,24 +55,27 @@ __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const i
   const int e = __builtin_amdgcn_readfirstlane(e_);
   const DevOp* __restrict__ op = S->op;
   const FT_CONST DevOp* cop = cptr(op);
-  if constexpr (KIND == kInterp18 || KIND == kInterp27) {
-    constexpr int R = KIND == kInterp18 ? 18 : 27;
+  if constexpr (KIND == kInterp9 || KIND == kInterp18 || KIND == kInterp27) {
+    constexpr int R = KIND == kInterp9 ? 9 : (KIND == kInterp18 ? 18 : 27);
+    constexpr int COPY = R >= 18 ? 13 : -1;
     if constexpr (MODE == 0)
-      apply_item<0, R, 0, 13, T, T, T>(
-          op, face, e, S->orientation, S->subface, S->coarse_offset, S->fine_offset, U, coarse,
-          coarse_elems, fine, fine_elems,
+      apply_item<0, R, 0, COPY, T, T, T>(
+          op, face, e, kFaceBuffers, S->orientation, S->subface, S->coarse_offset,
+          S->fine_offset, U, coarse, coarse_elems, fine, fine_elems,
           (const T*)(sizeof(T) == 8 ? (const void*)cop->w64 : (const void*)cop->w32), S->errors);
     else
-      mfma_item<R, 0, MODE>(op, face, e, wave, tile_all, S->orientation, S->subface,
-                            S->coarse_offset, S->fine_offset, U, (const float*)coarse,
+      mfma_item<R, 0, MODE>(op, face, e, kFaceBuffers, wave, tile_all, S->orientation,
+                            S->subface, S->coarse_offset, S->fine_offset, U, (const float*)coarse,
                             coarse_elems, (float*)fine, fine_elems, S->errors);
   } else {
-    constexpr int R = (KIND == kRestrict2Inject || KIND == kRestrict2Plain) ? 2 : 3;
+    constexpr int R = KIND == kRestrict1Plain
+                          ? 1
+                          : ((KIND == kRestrict2Inject || KIND == kRestrict2Plain) ? 2 : 3);
     constexpr int COPY = (KIND == kRestrict2Inject || KIND == kRestrict3Inject) ? 0 : -1;
-    apply_item<1, R, 0, COPY, T, double, double>(op, face, e, S->orientation, S->subface,
-                                                 S->fine_offset, S->coarse_offset, U, fine,
-                                                 fine_elems, coarse, coarse_elems, cop->w64,
-                                                 S->errors);
+    apply_item<1, R, 0, COPY, T, double, double>(op, face, e, kFaceBuffers, S->orientation,
+                                                 S->subface, S->fine_offset, S->coarse_offset,
+                                                 U, fine, fine_elems, coarse, coarse_elems,
+                                                 cop->w64, S->errors);
   }
 }
 
@@ -110,6 +122,8 @@ __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ s
       case kRestrict2Inject: FT_PLAN_LOOP(kRestrict2Inject)
       case kRestrict2Plain: FT_PLAN_LOOP(kRestrict2Plain)
       case kRestrict3Inject: FT_PLAN_LOOP(kRestrict3Inject)
+      case kInterp9: FT_PLAN_LOOP(kInterp9)
+      case kRestrict1Plain: FT_PLAN_LOOP(kRestrict1Plain)
       default: FT_PLAN_LOOP(kRestrict3Plain)
 #undef FT_PLAN_LOOP
     }
@@ -155,6 +169,8 @@ __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restric
     case kRestrict2Inject: plan_item<T, MODE, kRestrict2Inject>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
     case kRestrict2Plain: plan_item<T, MODE, kRestrict2Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
     case kRestrict3Inject: plan_item<T, MODE, kRestrict3Inject>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp9: plan_item<T, MODE, kInterp9>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict1Plain: plan_item<T, MODE, kRestrict1Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
     default: plan_item<T, MODE, kRestrict3Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
   }
 }
@@ -198,7 +214,9 @@ int heavy_of(int64_t s) { return (int)((s >> 17) & 1); }
 int persistent_of(int64_t s) { return (int)((s >> 18) & 1); }
 
 int plan_kind(const ft_operator* op) {
-  if (op->direction == FT_INTERPOLATE) return op->k == 2 ? ft::kInterp18 : ft::kInterp27;
+  if (op->direction == FT_INTERPOLATE)
+    return op->k == 1 ? ft::kInterp9 : (op->k == 2 ? ft::kInterp18 : ft::kInterp27);
+  if (op->k == 1) return ft::kRestrict1Plain;
   const bool inject = op->copy_row == 0;
   if (op->k == 2) return inject ? ft::kRestrict2Inject : ft::kRestrict2Plain;
   return inject ? ft::kRestrict3Inject : ft::kRestrict3Plain;

@@ -21,6 +21,9 @@ Workloads (all seeds are 15814 + workload number; draw order is fixed below):
 3  workload 2 with unknown u (field and noise) scaled by 10^(-6 + 9 u / 58).
 4  50,000 faces: p in {6, 9, 12} at 30/50/20 %, k in {2, 3}, scheme and
    direction uniform, U = 59, fields as workload 2.
+5  three seeded 3-level AMR meshes (see workload5).
+6  hanging faces between patches with halos (see patch_transitions): 6,003
+   fine patches of 9^3 cells, nine per coarse face, k = 3, U = 59.
 Faces sit on a grid of 9^3 coarse patches (h_c = 1/81, h_f = 1/243).
 """
 
@@ -321,15 +324,23 @@ class MixedBatch:
                 self.coarse_offset[i].contiguous(), self.fine_offset[i].contiguous())
 
 
-def workload4(n_faces=50000, device="cpu", dtype=torch.float32, U=59, seed=SEED_BASE + 4):
+def workload4(n_faces=50000, device="cpu", dtype=torch.float32, U=59, seed=SEED_BASE + 4,
+              k_values=(2, 3)):
     """50,000 faces: p in {6, 9, 12} at 30/50/20 %, k in {2, 3} uniform, scheme
     in {d-linear, Taylor-2, Taylor-3} uniform, direction Bernoulli(1/2)
-    interleaved; bump fields with 1e-3 noise, U = 59."""
+    interleaved; bump fields with 1e-3 noise, U = 59.  Other halo depths can
+    be mixed in with k_values (uniform over them); faces drawn with k = 1
+    use the d-linear scheme, the only one defined there."""
     gen = torch.Generator().manual_seed(seed)
     r = torch.rand(n_faces, generator=gen)
     p = torch.where(r < 0.3, 6, torch.where(r < 0.8, 9, 12)).to(torch.int64)
-    k = torch.randint(2, 4, (n_faces,), generator=gen)
+    if tuple(k_values) == (2, 3):
+        k = torch.randint(2, 4, (n_faces,), generator=gen)
+    else:
+        kv = torch.tensor(k_values, dtype=torch.int64)
+        k = kv[torch.randint(0, len(k_values), (n_faces,), generator=gen)]
     scheme = torch.randint(1, 4, (n_faces,), generator=gen)
+    scheme = torch.where(k == 1, torch.ones_like(scheme), scheme)
     direction = torch.randint(0, 2, (n_faces,), generator=gen)
     orient = torch.randint(0, 6, (n_faces,), generator=gen)
     sub = torch.randint(0, 9, (n_faces,), generator=gen)
@@ -344,7 +355,7 @@ def workload4(n_faces=50000, device="cpu", dtype=torch.float32, U=59, seed=SEED_
     noise_seed = int(torch.randint(0, 2**62, (1,), generator=gen).item())
     noise_gen = torch.Generator(device=device).manual_seed(noise_seed)
     for pp in (6, 9, 12):
-        for kk in (2, 3):
+        for kk in k_values:
             sel = torch.nonzero((p == pp) & (k == kk)).flatten()
             if sel.numel() == 0:
                 continue
@@ -539,3 +550,59 @@ def workload5(n_meshes=3, p=9, k=3, U=59, device="cpu", dtype=torch.float64, see
             where = (coff[sel].to(dev)[:, None] + torch.arange(E, device=dev)[None, :]).reshape(-1)
             mf.coarse[where] = vc.reshape(-1).to(dtype)
     return mf
+
+
+@dataclass
+class PatchTransitions:
+    """Hanging faces between patches (boxes of (p + 2k)^3 cells, interior
+    [k, k + p) per axis, axis 0 fastest, unknowns innermost).  Face i joins
+    the coarse patch at coarse_offset[i] of `coarse` to the fine patch at
+    fine_offset[i] of `fine` (element offsets); fine patches are not shared,
+    coarse patches are shared by `faces_per_coarse` faces that sit on one
+    coarse face (one orientation, distinct subfaces)."""
+
+    p: int
+    k: int
+    U: int
+    orientation: torch.Tensor
+    subface: torch.Tensor
+    coarse_offset: torch.Tensor
+    fine_offset: torch.Tensor
+    coarse: torch.Tensor
+    fine: torch.Tensor
+
+    @property
+    def n(self):
+        return int(self.orientation.numel())
+
+    @property
+    def patch_elems(self):
+        return (self.p + 2 * self.k) ** 3 * self.U
+
+
+def patch_transitions(n_faces, p, k, U, seed, device="cpu", dtype=torch.float64, faces_per_coarse=1):
+    """Seeded patches for the fused transfer.  Draw order: orientation and
+    subface per group (CPU torch generator seeded `seed`), then the coarse
+    pool and the fine pool as standard normal values drawn on `device` by a
+    generator of that device seeded `seed` (the transfer is linear, so the
+    data only need to be finite; every cell of every patch is filled,
+    including edge and vertex cells that no call touches)."""
+    if faces_per_coarse not in (1, 9):
+        raise ValueError("faces_per_coarse must be 1 or 9")
+    gen = torch.Generator().manual_seed(seed)
+    groups = -(-n_faces // faces_per_coarse)
+    o_g = torch.randint(0, 6, (groups,), generator=gen)
+    if faces_per_coarse == 9:
+        sub = torch.stack([torch.randperm(9, generator=gen) for _ in range(groups)]).reshape(-1)
+    else:
+        sub = torch.randint(0, 9, (groups,), generator=gen)
+    orientation = o_g.repeat_interleave(faces_per_coarse)[:n_faces].to(torch.int8)
+    subface = sub[:n_faces].to(torch.int8)
+    P3U = (p + 2 * k) ** 3 * U
+    coarse_offset = (torch.arange(n_faces) // faces_per_coarse * P3U).to(torch.int64)
+    fine_offset = (torch.arange(n_faces) * P3U).to(torch.int64)
+    dgen = torch.Generator(device=device).manual_seed(seed)
+    coarse = torch.randn(groups * P3U, generator=dgen, dtype=dtype, device=device)
+    fine = torch.randn(n_faces * P3U, generator=dgen, dtype=dtype, device=device)
+    return PatchTransitions(p, k, U, orientation.to(device), subface.to(device),
+                            coarse_offset.to(device), fine_offset.to(device), coarse, fine)

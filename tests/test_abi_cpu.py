@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol():
 
 
 def test_version_and_empty_error():
-    assert api.transfer_version() == 100
+    assert api.transfer_version() == 200
     assert isinstance(api.transfer_last_error(), str)
 
 
@@ -177,3 +177,61 @@ def test_schedule_packing_roundtrip():
     s = api.pack_schedule(2, 16, 1, 1, 0)
     assert api.unpack_schedule(s) == {"waves_per_block": 2, "blocks_per_cu": 16, "xcd_remap": 1, "heavy_first": 1,
                                       "persistent": 0}
+
+
+def test_patch_copy_checks_happen_on_host():
+    """Host-side rejections of the patch / face-buffer copies (nothing is
+    launched: every case fails before a HIP call)."""
+    lib = _lib.load()
+    q = ctypes.c_void_p(16)
+    r = ctypes.c_void_p(32)
+
+    def gather(p=9, k=3, n=1, sel=q, halves=api.FT_HALF_BOTH, U=59, dtype=0, src=q, dst=r):
+        return lib.gather_patch_faces(p, k, n, sel, q, q, halves, U, dtype, src, 10**6, dst, 10**6, None, None)
+
+    assert gather(p=0) == api.FT_ERR_UNSUPPORTED
+    assert gather(k=0) == api.FT_ERR_UNSUPPORTED
+    assert gather(p=2, k=3) == api.FT_ERR_UNSUPPORTED  # k > p
+    assert gather(U=0) == api.FT_ERR_UNSUPPORTED
+    assert gather(dtype=7) == api.FT_ERR_UNSUPPORTED
+    assert gather(halves=0) == api.FT_ERR_INVALID
+    assert gather(halves=4) == api.FT_ERR_INVALID
+    assert gather(n=-1) == api.FT_ERR_INVALID
+    assert gather(sel=None) == api.FT_ERR_INVALID
+    assert gather(src=r) == api.FT_ERR_INVALID  # alias
+    assert gather(n=0, sel=None) == api.FT_OK  # empty call is a no-op
+    assert lib.scatter_patch_faces(9, 3, 1, q, q, q, 3, 59, 0, q, 10**6, q, 10**6, None, None) == api.FT_ERR_INVALID
+    assert lib.copy_patch_halos(9, 3, 1, None, q, q, 59, 0, q, 10**6, None, None) == api.FT_ERR_INVALID
+    assert lib.copy_patch_halos(9, 0, 1, q, q, q, 59, 0, q, 10**6, None, None) == api.FT_ERR_UNSUPPORTED
+    assert lib.copy_patch_halos(9, 3, 0, None, None, None, 59, 0, q, 10**6, None, None) == api.FT_OK
+
+
+def test_patch_transfer_needs_device_operator():
+    lib = _lib.load()
+    op = api.build_transfer_operator(0, 3, 9, 3, api.FT_BUILD_HOST_ONLY)
+    rop = api.build_transfer_operator(1, 3, 9, 3, api.FT_BUILD_HOST_ONLY)
+    p = ctypes.c_void_p(16)
+    args = (1, p, p, p, p, 59, 0, p, 10**6, p, 10**6, None)
+    assert lib.interpolate_patches(op.handle, *args) == api.FT_ERR_INVALID  # host-only operator
+    assert lib.interpolate_patches(rop.handle, *args) == api.FT_ERR_INVALID  # wrong direction
+    assert lib.restrict_patches(op.handle, *args) == api.FT_ERR_INVALID
+    assert lib.interpolate_patches(None, *args) == api.FT_ERR_INVALID
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("p", [6, 9, 12])
+def test_library_segments_equal_oracle_k1(direction, p):
+    """Halo depth 1 (finite volumes), d-linear: maps exact, weights equal."""
+    test_library_segments_equal_oracle(direction, 1, p, 1)
+
+
+def test_k1_only_for_dlinear():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    for scheme in (2, 3):
+        assert lib.build_transfer_operator(0, scheme, 9, 1, api.FT_BUILD_HOST_ONLY, ctypes.byref(h)) == api.FT_ERR_UNSUPPORTED
+    op = api.build_transfer_operator(0, 1, 9, 1, api.FT_BUILD_HOST_ONLY)
+    info = op.info()
+    assert info["rows_per_anchor"] == 9 and info["k"] == 1
+    rop = api.build_transfer_operator(1, 1, 9, 1, api.FT_BUILD_HOST_ONLY)
+    assert rop.info()["rows_per_anchor"] == 1

@@ -69,6 +69,15 @@ def test_matrix_core_path_shapes(dev, p, k, U):
     check_mode(batch, 1, api.FT_F32_BF16X3)
 
 
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("U", [7, 59])
+def test_halo_depth_one_modes(dev, mode, U):
+    """k = 1 (d-linear, 9 rows per anchor, no exact-copy row) in every
+    float32 mode."""
+    batch = wl.uniform_faces(20, 9, 1, U, seed=91 + U + mode, device=dev)
+    check_mode(batch, 1, mode)
+
+
 def test_restriction_modes_share_the_float32_path(b59):
     outs = []
     for mode in MODES:

@@ -66,6 +66,17 @@ def test_shapes_and_ragged_unknowns(dev, p, k, U):
             gh.check_parity(direction, scheme, batch)
 
 
+@pytest.mark.parametrize("p", [6, 9, 12])
+@pytest.mark.parametrize("U", [1, 59, 70])
+def test_halo_depth_one_dlinear(dev, p, U):
+    """k = 1 (finite volumes): the d-linear scheme, both directions, float64
+    and float32 storage."""
+    batch = wl.uniform_faces(30, p, 1, U, seed=2000 + p + U, device=dev)
+    for direction in DIRS:
+        gh.check_parity(direction, 1, batch)
+        gh.check_parity(direction, 1, batch, dtype=torch.float32, tol=1e-5)
+
+
 def test_empty_batch_is_a_noop(dev):
     batch = wl.uniform_faces(3, 9, 3, 5, seed=3, device=dev)
     for direction in DIRS:

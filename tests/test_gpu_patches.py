@@ -1,0 +1,368 @@
+"""GPU parity of the patch entry points (gather / scatter of face views, the
+same-level halo exchange, and the transfer fused with the patches) against
+the oracle's patch functions, called through the C ABI.
+
+Copies are compared bit for bit.  The fused transfer is compared with the
+oracle (float64: 1e-12 of the largest written value per unknown) and, in
+every mode, bit for bit with the unfused GPU composition (gather the face
+views, apply the face-buffer transfer, scatter the halo half): both run the
+same arithmetic in the same order, only the addressing differs.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import patches as opt
+from paper_2504_15814_amd import api
+from paper_2504_15814_amd.workloads import patch_transitions
+from tests.gpu_helpers import SENTINEL, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+BOTH, INNER, OUTER = api.FT_HALF_BOTH, api.FT_HALF_INNER, api.FT_HALF_OUTER
+
+
+def npy(t):
+    return t.double().cpu().numpy()
+
+
+def face_elems(p, k, U):
+    return 2 * k * p * p * U
+
+
+def written_halo_mask(p, k, U, faces, offsets, n_elems):
+    """Elements of the outer halves of the given patch faces (from the
+    oracle's scatter of a buffer of ones)."""
+    fe = face_elems(p, k, U)
+    ones = np.ones(len(faces) * fe)
+    zero = np.zeros(n_elems)
+    out = opt.scatter_patch_faces(p, k, faces, offsets, np.arange(len(faces)) * fe, U, OUTER, ones, zero)
+    return out != 0
+
+
+@pytest.mark.parametrize("p,k,U", [(6, 2, 7), (9, 3, 59), (12, 3, 70)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("halves", [INNER, OUTER, BOTH])
+def test_gather_scatter_parity(p, k, U, dtype, halves):
+    dev = require_gpu()
+    b = patch_transitions(12, p, k, U, seed=101 + p + halves, device=dev, dtype=dtype)
+    n = b.n
+    fe = face_elems(p, k, U)
+    gen = torch.Generator().manual_seed(7)
+    face = torch.randint(0, 6, (n,), generator=gen).to(torch.int8).to(dev)
+    face_off = (torch.arange(n, dtype=torch.int64) * fe).to(dev)
+    # (the sentinel is rounded to the storage type: start the oracle from
+    # the same values)
+    faces = torch.full((n * fe,), SENTINEL, dtype=dtype, device=dev)
+    faces_before = npy(faces)
+    skipped = torch.zeros(1, dtype=torch.int32, device=dev)
+    api.gather_patch_faces(p, k, face, b.fine_offset, face_off, halves, U, b.fine, faces, skipped)
+    torch.cuda.synchronize()
+    want = opt.gather_patch_faces(p, k, face.cpu().numpy(), b.fine_offset.cpu().numpy(),
+                                  face_off.cpu().numpy(), U, halves, npy(b.fine), faces_before)
+    assert np.array_equal(npy(faces), want)
+
+    pool = torch.full_like(b.fine, SENTINEL)
+    pool_before = npy(pool)
+    api.scatter_patch_faces(p, k, face, b.fine_offset, face_off, halves, U, faces, pool, skipped)
+    torch.cuda.synchronize()
+    want2 = opt.scatter_patch_faces(p, k, face.cpu().numpy(), b.fine_offset.cpu().numpy(),
+                                    face_off.cpu().numpy(), U, halves, want, pool_before)
+    assert np.array_equal(npy(pool), want2)
+    assert int(skipped.item()) == 0
+
+
+def test_copy_bad_items_are_skipped_and_counted():
+    dev = require_gpu()
+    p, k, U = 9, 3, 5
+    b = patch_transitions(4, p, k, U, seed=5, device=dev)
+    fe = face_elems(p, k, U)
+    face = torch.tensor([0, 6, 3, -1], dtype=torch.int8, device=dev)
+    po = b.fine_offset.clone()
+    po[2] = b.fine.numel()  # past the end
+    face_off = (torch.arange(4, dtype=torch.int64) * fe).to(dev)
+    faces = torch.full((4 * fe,), SENTINEL, dtype=torch.float64, device=dev)
+    skipped = torch.zeros(1, dtype=torch.int32, device=dev)
+    api.gather_patch_faces(p, k, face, po, face_off, BOTH, U, b.fine, faces, skipped)
+    torch.cuda.synchronize()
+    assert int(skipped.item()) == 3
+    got = npy(faces)
+    assert np.all(got[fe:] == SENTINEL)  # items 1..3 wrote nothing
+    want = opt.gather_patch_faces(p, k, [0], [int(po[0])], [0], U, BOTH, npy(b.fine), np.full(fe, SENTINEL))
+    assert np.array_equal(got[:fe], want)
+
+
+def halo_pairs(m, n_pairs, seed):
+    """Pairs (axis, lower, upper) of distinct patches such that no (patch,
+    face) halo is written twice."""
+    rng = np.random.default_rng(seed)
+    used = set()
+    pairs = []
+    while len(pairs) < n_pairs:
+        a = int(rng.integers(0, 3))
+        lo, hi = (int(v) for v in rng.choice(m, 2, replace=False))
+        if (lo, a + 3) in used or (hi, a) in used:
+            continue
+        used.add((lo, a + 3))
+        used.add((hi, a))
+        pairs.append((a, lo, hi))
+    return pairs
+
+
+@pytest.mark.parametrize("p,k,U", [(6, 2, 3), (9, 3, 59), (12, 3, 64)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_copy_patch_halos_parity(p, k, U, dtype):
+    dev = require_gpu()
+    m = 10
+    b = patch_transitions(m, p, k, U, seed=11 + p, device=dev, dtype=dtype)
+    pairs = halo_pairs(m, 12, seed=p)
+    P3U = b.patch_elems
+    axis = torch.tensor([a for a, _, _ in pairs], dtype=torch.int8, device=dev)
+    lower = torch.tensor([lo * P3U for _, lo, _ in pairs], dtype=torch.int64, device=dev)
+    upper = torch.tensor([hi * P3U for _, _, hi in pairs], dtype=torch.int64, device=dev)
+    before = npy(b.fine)
+    pool = b.fine.clone()
+    skipped = torch.zeros(1, dtype=torch.int32, device=dev)
+    api.copy_patch_halos(p, k, axis, lower, upper, U, pool, skipped)
+    torch.cuda.synchronize()
+    want = opt.copy_patch_halos(p, k, axis.cpu().numpy(), lower.cpu().numpy(), upper.cpu().numpy(), U, before)
+    assert np.array_equal(npy(pool), want)
+    assert int(skipped.item()) == 0
+
+
+def unfused_interpolate(op, b, coarse, fine, mode=None):
+    """Gather each coarse face view, interpolate face buffers, scatter the
+    fine ghost halves (all on the GPU)."""
+    p, k, U, n = b.p, b.k, b.U, b.n
+    fe = face_elems(p, k, U)
+    dev = coarse.device
+    offs = (torch.arange(n, dtype=torch.int64) * fe).to(dev)
+    cface = ((b.orientation.to(torch.int64) + 3) % 6).to(torch.int8)
+    cbuf = torch.zeros(n * fe, dtype=coarse.dtype, device=dev)
+    fbuf = torch.zeros(n * fe, dtype=coarse.dtype, device=dev)
+    api.gather_patch_faces(p, k, cface, b.coarse_offset, offs, BOTH, U, coarse, cbuf)
+    api.interpolate_faces(op, b.orientation, b.subface, offs, offs, U, cbuf, fbuf, mode=mode)
+    api.scatter_patch_faces(p, k, b.orientation, b.fine_offset, offs, OUTER, U, fbuf, fine)
+
+
+def unfused_restrict(op, b, fine, coarse, faces_per_coarse):
+    """Gather each fine face view, restrict into one face buffer per coarse
+    face, scatter those buffers' halo halves."""
+    p, k, U, n = b.p, b.k, b.U, b.n
+    fe = face_elems(p, k, U)
+    dev = coarse.device
+    offs = (torch.arange(n, dtype=torch.int64) * fe).to(dev)
+    groups = -(-n // faces_per_coarse)
+    goffs = (torch.arange(n, dtype=torch.int64) // faces_per_coarse * fe).to(dev)
+    fbuf = torch.zeros(n * fe, dtype=coarse.dtype, device=dev)
+    cbuf = torch.zeros(groups * fe, dtype=coarse.dtype, device=dev)
+    cface = ((b.orientation.to(torch.int64) + 3) % 6).to(torch.int8)
+    first = torch.arange(0, n, faces_per_coarse, device=dev)
+    gface = cface[first].contiguous()
+    gpatch = b.coarse_offset[first].contiguous()
+    gbuf = goffs[first].contiguous()
+    api.gather_patch_faces(p, k, gface, gpatch, gbuf, BOTH, U, coarse, cbuf)
+    api.gather_patch_faces(p, k, b.orientation, b.fine_offset, offs, BOTH, U, fine, fbuf)
+    api.restrict_faces(op, b.orientation, b.subface, goffs, offs, U, fbuf, cbuf)
+    api.scatter_patch_faces(p, k, gface, gpatch, gbuf, OUTER, U, cbuf, coarse)
+
+
+SHAPES = [(6, 2, 7), (9, 3, 59), (12, 3, 70)]
+
+
+@pytest.mark.parametrize("scheme", [oracle.DLINEAR, oracle.TAYLOR2, oracle.TAYLOR3])
+@pytest.mark.parametrize("p,k,U", SHAPES)
+def test_interpolate_patches_parity(scheme, p, k, U):
+    dev = require_gpu()
+    b = patch_transitions(18, p, k, U, seed=300 + scheme + p, device=dev, faces_per_coarse=9)
+    op = api.build_transfer_operator(0, scheme, p, k)
+    before = npy(b.fine)
+    fine = b.fine.clone()
+    api.interpolate_patches(op, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, b.coarse, fine)
+    torch.cuda.synchronize()
+    assert op.errors() == 0
+    got = npy(fine)
+    o, s = b.orientation.cpu().numpy(), b.subface.cpu().numpy()
+    co, fo = b.coarse_offset.cpu().numpy(), b.fine_offset.cpu().numpy()
+    want = opt.interpolate_patches(scheme, p, k, o, s, co, fo, U, npy(b.coarse), before)
+    mask = written_halo_mask(p, k, U, o, fo, len(before))
+    assert np.array_equal(got[~mask], before[~mask])
+    d = np.abs(got[mask] - want[mask]).reshape(-1, U).max(axis=0)
+    scale = np.abs(want[mask]).reshape(-1, U).max(axis=0)
+    assert (d / scale).max() <= 1e-12
+    # the unfused GPU composition gives the same bits
+    ref = b.fine.clone()
+    unfused_interpolate(op, b, b.coarse, ref)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, fine)
+
+
+@pytest.mark.parametrize("mode", [api.FT_F32, api.FT_F32_BF16X3, api.FT_F32_BF16X6])
+@pytest.mark.parametrize("p,k,U", [(9, 3, 59), (12, 3, 70)])
+def test_interpolate_patches_float32_matches_unfused(mode, p, k, U):
+    dev = require_gpu()
+    b = patch_transitions(27, p, k, U, seed=400 + mode, device=dev, dtype=torch.float32, faces_per_coarse=9)
+    op = api.build_transfer_operator(0, oracle.TAYLOR3, p, k)
+    fine = b.fine.clone()
+    api.interpolate_patches(op, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, b.coarse, fine,
+                            mode=mode)
+    ref = b.fine.clone()
+    unfused_interpolate(op, b, b.coarse, ref, mode=mode)
+    torch.cuda.synchronize()
+    assert op.errors() == 0
+    assert torch.equal(ref, fine)
+    # and it is close to the float64 oracle on the same (float32) inputs
+    got = npy(fine)
+    o, s = b.orientation.cpu().numpy(), b.subface.cpu().numpy()
+    co, fo = b.coarse_offset.cpu().numpy(), b.fine_offset.cpu().numpy()
+    want = opt.interpolate_patches(oracle.TAYLOR3, p, k, o[:9], s[:9], co[:9], fo[:9], U, npy(b.coarse), npy(b.fine))
+    mask = written_halo_mask(p, k, U, o[:9], fo[:9], len(got))
+    tol = {api.FT_F32: 5e-5, api.FT_F32_BF16X3: 5e-3, api.FT_F32_BF16X6: 5e-5}[mode]
+    err = np.abs(got[mask] - want[mask]).max() / np.abs(want[mask]).max()
+    assert err <= tol, err
+
+
+@pytest.mark.parametrize("scheme", [oracle.DLINEAR, oracle.TAYLOR2, oracle.TAYLOR3])
+@pytest.mark.parametrize("p,k,U", SHAPES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_restrict_patches_parity(scheme, p, k, U, dtype):
+    """Nine fine patches per coarse face write disjoint segments of one halo."""
+    dev = require_gpu()
+    b = patch_transitions(18, p, k, U, seed=500 + scheme + p, device=dev, dtype=dtype, faces_per_coarse=9)
+    op = api.build_transfer_operator(1, scheme, p, k)
+    before = npy(b.coarse)
+    coarse = b.coarse.clone()
+    api.restrict_patches(op, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, b.fine, coarse)
+    torch.cuda.synchronize()
+    assert op.errors() == 0
+    got = npy(coarse)
+    o, s = b.orientation.cpu().numpy(), b.subface.cpu().numpy()
+    co, fo = b.coarse_offset.cpu().numpy(), b.fine_offset.cpu().numpy()
+    want = opt.restrict_patches(scheme, p, k, o, s, co, fo, U, npy(b.fine), before)
+    cf = (o.astype(np.int64) + 3) % 6
+    mask = written_halo_mask(p, k, U, cf[::9], co[::9], len(before))
+    assert np.array_equal(got[~mask], before[~mask])
+    d = np.abs(got[mask] - want[mask]).reshape(-1, U).max(axis=0)
+    scale = np.abs(want[mask]).reshape(-1, U).max(axis=0)
+    # float32 storage: restriction sums run in float64 on float32 inputs; the
+    # result is rounded once to float32
+    tol = 1e-12 if dtype == torch.float64 else 2 ** -23
+    assert (d / scale).max() <= tol
+    ref = b.coarse.clone()
+    unfused_restrict(op, b, b.fine, ref, 9)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, coarse)
+
+
+def test_patches_in_one_pool():
+    """Coarse and fine patches in one tensor: same result as two tensors."""
+    dev = require_gpu()
+    p, k, U = 9, 3, 59
+    b = patch_transitions(9, p, k, U, seed=77, device=dev, faces_per_coarse=9)
+    nc = b.coarse.numel()
+    pool = torch.cat([b.coarse, b.fine])
+    fo = b.fine_offset + nc
+    iop = api.build_transfer_operator(0, oracle.TAYLOR3, p, k)
+    rop = api.build_transfer_operator(1, oracle.TAYLOR3, p, k)
+    api.restrict_patches(rop, b.orientation, b.subface, b.coarse_offset, fo, U, pool, pool)
+    api.interpolate_patches(iop, b.orientation, b.subface, b.coarse_offset, fo, U, pool, pool)
+    coarse, fine = b.coarse.clone(), b.fine.clone()
+    api.restrict_patches(rop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, fine, coarse)
+    api.interpolate_patches(iop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, coarse, fine)
+    torch.cuda.synchronize()
+    assert torch.equal(pool[:nc], coarse) and torch.equal(pool[nc:], fine)
+    assert iop.errors() == 0 and rop.errors() == 0
+
+
+def test_patch_transfer_bad_descriptors_and_empty():
+    dev = require_gpu()
+    p, k, U = 6, 2, 4
+    b = patch_transitions(3, p, k, U, seed=9, device=dev)
+    op = api.build_transfer_operator(0, oracle.TAYLOR2, p, k)
+    o = b.orientation.clone()
+    o[1] = 9
+    fo = b.fine_offset.clone()
+    fo[2] = b.fine.numel() - 5
+    fine = b.fine.clone()
+    api.interpolate_patches(op, o, b.subface, b.coarse_offset, fo, U, b.coarse, fine)
+    torch.cuda.synchronize()
+    assert op.errors() == 2
+    # face 0 alone, as the oracle computes it; faces 1 and 2 wrote nothing
+    want = opt.interpolate_patches(oracle.TAYLOR2, p, k, o[:1].cpu().numpy(), b.subface[:1].cpu().numpy(),
+                                   b.coarse_offset[:1].cpu().numpy(), fo[:1].cpu().numpy(), U,
+                                   npy(b.coarse), npy(b.fine))
+    got = npy(fine)
+    mask = written_halo_mask(p, k, U, o[:1].cpu().numpy(), fo[:1].cpu().numpy(), len(got))
+    assert np.array_equal(got[~mask], npy(b.fine)[~mask])
+    assert np.abs(got[mask] - want[mask]).max() <= 1e-12 * np.abs(want[mask]).max()
+    e8 = torch.zeros(0, dtype=torch.int8, device=dev)
+    e64 = torch.zeros(0, dtype=torch.int64, device=dev)
+    api.interpolate_patches(op, e8, e8, e64, e64, U, b.coarse, fine)
+    api.gather_patch_faces(p, k, e8, e64, e64, BOTH, U, b.fine, b.coarse)
+    api.copy_patch_halos(p, k, e8, e64, e64, U, fine)
+
+
+def test_full_size_patch_transfer_sampled():
+    """2,000 hanging faces at p=9, k=3, U=59 in float64 (the benchmark's
+    patch configuration), nine per coarse face: sampled faces against the
+    oracle, every face against the unfused GPU composition."""
+    dev = require_gpu()
+    p, k, U = 9, 3, 59
+    b = patch_transitions(2000, p, k, U, seed=15814 + 6, device=dev, faces_per_coarse=9)
+    iop = api.build_transfer_operator(0, oracle.TAYLOR3, p, k)
+    rop = api.build_transfer_operator(1, oracle.TAYLOR3, p, k)
+    fine, coarse = b.fine.clone(), b.coarse.clone()
+    api.restrict_patches(rop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, fine, coarse)
+    api.interpolate_patches(iop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, coarse, fine)
+    rc, rf = b.coarse.clone(), b.fine.clone()
+    unfused_restrict(rop, b, rf, rc, 9)
+    unfused_interpolate(iop, b, rc, rf)
+    torch.cuda.synchronize()
+    assert torch.equal(rc, coarse) and torch.equal(rf, fine)
+    P3U = b.patch_elems
+    for i in (0, 4, 999, 1998):
+        c0 = int(b.coarse_offset[i])
+        f0 = int(b.fine_offset[i])
+        o, s = [int(b.orientation[i])], [int(b.subface[i])]
+        src = npy(coarse[c0 : c0 + P3U])
+        want = opt.interpolate_patches(oracle.TAYLOR3, p, k, o, s, [0], [0], U, src, npy(b.fine[f0 : f0 + P3U]))
+        got = npy(fine[f0 : f0 + P3U])
+        mask = written_halo_mask(p, k, U, o, [0], P3U)
+        assert np.abs(got[mask] - want[mask]).max() <= 1e-12 * np.abs(want[mask]).max()
+
+
+@pytest.mark.parametrize("p,U", [(6, 5), (9, 59)])
+def test_patches_halo_depth_one(p, U):
+    """k = 1 (finite volumes, d-linear): fused transfer against the oracle and
+    the unfused composition, and the same-level halo copy."""
+    dev = require_gpu()
+    k = 1
+    b = patch_transitions(18, p, k, U, seed=600 + p, device=dev, faces_per_coarse=9)
+    iop = api.build_transfer_operator(0, oracle.DLINEAR, p, k)
+    rop = api.build_transfer_operator(1, oracle.DLINEAR, p, k)
+    o, s = b.orientation.cpu().numpy(), b.subface.cpu().numpy()
+    co, fo = b.coarse_offset.cpu().numpy(), b.fine_offset.cpu().numpy()
+    coarse, fine = b.coarse.clone(), b.fine.clone()
+    api.restrict_patches(rop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, fine, coarse)
+    api.interpolate_patches(iop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, coarse, fine)
+    rc, rf = b.coarse.clone(), b.fine.clone()
+    unfused_restrict(rop, b, rf, rc, 9)
+    unfused_interpolate(iop, b, rc, rf)
+    torch.cuda.synchronize()
+    assert torch.equal(rc, coarse) and torch.equal(rf, fine)
+    want_c = opt.restrict_patches(oracle.DLINEAR, p, k, o, s, co, fo, U, npy(b.fine), npy(b.coarse))
+    want_f = opt.interpolate_patches(oracle.DLINEAR, p, k, o, s, co, fo, U, want_c, npy(b.fine))
+    for got, want in ((npy(coarse), want_c), (npy(fine), want_f)):
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    pairs = halo_pairs(18, 10, seed=3)
+    P3U = b.patch_elems
+    axis = torch.tensor([a for a, _, _ in pairs], dtype=torch.int8, device=dev)
+    lower = torch.tensor([lo * P3U for _, lo, _ in pairs], dtype=torch.int64, device=dev)
+    upper = torch.tensor([hi * P3U for _, _, hi in pairs], dtype=torch.int64, device=dev)
+    pool = b.fine.clone()
+    api.copy_patch_halos(p, k, axis, lower, upper, U, pool)
+    torch.cuda.synchronize()
+    want = opt.copy_patch_halos(p, k, axis.cpu().numpy(), lower.cpu().numpy(), upper.cpu().numpy(), U, npy(b.fine))
+    assert np.array_equal(npy(pool), want)

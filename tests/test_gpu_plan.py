@@ -187,3 +187,18 @@ def test_restrict_first_plan_and_multi_step_graph(dev):
         plan.run()
     torch.cuda.synchronize()
     assert torch.equal(coarse, rc) and torch.equal(fine, rf)
+
+
+def test_plan_with_halo_depth_one(dev):
+    """A mix with k in {1, 2, 3} (k = 1 faces are d-linear): the plan equals
+    the per-batch calls bit for bit in every float32 mode and in float64."""
+    for dtype, modes in ((torch.float32, (api.FT_F32, api.FT_F32_BF16X6)), (torch.float64, (None,))):
+        mb = wl.workload4(n_faces=900, device=dev, dtype=dtype, seed=123, k_values=(1, 2, 3))
+        assert any(key[3] == 1 for key in mb.groups())
+        ops = build_ops(mb)
+        for mode in modes:
+            rc, rf = per_batch_reference(mb, ops, mode)
+            _, pc, pf = run_plan(mb, ops, mode)
+            assert torch.equal(pc, rc) and torch.equal(pf, rf)
+        for op in ops.values():
+            assert op.errors() == 0
