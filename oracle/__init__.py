@@ -19,6 +19,8 @@ transfer   dense per-subface operators built directly in each physical
            (Section 2, the P / R matrices and their 1/9 segments)
 patches    patches with face halos: face views, the same-level halo copy, and
            the transfer composed with them (Section 2)
+transfer2d the same transfer in two dimensions (Sections 2-3 are stated for
+           any dimension)
 
 Everything is float64 and written for readability, not speed.
 """
@@ -49,6 +51,7 @@ from .transfer import (
     clear_operator_cache,
 )
 from . import patches
+from . import transfer2d
 
 __all__ = [
     "face_axes",
@@ -77,4 +80,5 @@ __all__ = [
     "restrict_faces",
     "clear_operator_cache",
     "patches",
+    "transfer2d",
 ]

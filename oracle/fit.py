@@ -1,7 +1,8 @@
 """Taylor fits and 1D linear weights (oracle; test infrastructure).
 
 Section 3 ("Operator construction"): per expansion cell, the derivatives up to
-order D (D = 2: n = 1 + 3 + 6 = 10 terms; D = 3: n = 20) are fitted from the
+order D (in 3D, D = 2: n = 1 + 3 + 6 = 10 terms, D = 3: n = 20; in 2D 6 and 10)
+are fitted from the
 values at a stencil of cell centres, giving an s x n system A x = Q that is
 solved with a QR decomposition ("standard matrix inversion"), and the fitted
 Taylor polynomial is evaluated at the target centres.
@@ -35,18 +36,19 @@ import numpy as np
 from scipy.linalg import solve_triangular
 
 
-def taylor_exponents(degree):
-    """Multi-indices alpha with 1 <= |alpha| <= degree (the non-constant terms)."""
+def taylor_exponents(degree, dim=3):
+    """Multi-indices alpha (dim components) with 1 <= |alpha| <= degree (the
+    non-constant terms)."""
     out = []
     for total in range(1, degree + 1):
-        for alpha in product(range(total + 1), repeat=3):
+        for alpha in product(range(total + 1), repeat=dim):
             if sum(alpha) == total:
                 out.append(alpha)
     return out
 
 
 def taylor_term(offset, alpha):
-    """Taylor basis term offset^alpha / alpha! for a 3-vector offset."""
+    """Taylor basis term offset^alpha / alpha! for an offset vector."""
     val = 1.0
     for d, e in zip(offset, alpha):
         val *= d**e / factorial(e)
@@ -56,12 +58,13 @@ def taylor_term(offset, alpha):
 def taylor_stencil(centre, ext, degree):
     """Stencil (list of index triples) for an expansion cell at `centre` inside a
     buffer of extents `ext` (Appendix C, reading above)."""
+    dim = len(centre)
     shifted = [min(max(int(ci), 1), int(e) - 2) for ci, e in zip(centre, ext)]
     pts = []
-    for d0, d1, d2 in product((-1, 0, 1), repeat=3):
-        pts.append((shifted[0] + d0, shifted[1] + d1, shifted[2] + d2))
+    for d in product((-1, 0, 1), repeat=dim):
+        pts.append(tuple(shifted[ax] + d[ax] for ax in range(dim)))
     if degree >= 3:
-        for ax in range(3):
+        for ax in range(dim):
             for step in (-2, 2):
                 q = list(shifted)
                 q[ax] += step
@@ -77,7 +80,7 @@ def _derivative_operator(offsets, centre_pos, degree):
     """QR solve of the pinned fit for one stencil: the matrix that maps the
     stencil values minus the centre value to the derivatives."""
     s = len(offsets)
-    exps = taylor_exponents(degree)
+    exps = taylor_exponents(degree, len(offsets[0]))
     others = [q for q in range(s) if q != centre_pos]
     # A: rows = stencil points other than the centre, columns = derivatives.
     A = np.array([[taylor_term(offsets[q], al) for al in exps] for q in others])
@@ -93,13 +96,13 @@ def pinned_fit_weights(offsets, centre_pos, target, degree):
     polynomial of degree `degree`, fitted with its constant pinned to the
     centre value, evaluated at `target`.
 
-    offsets    : (s, 3) stencil offsets from the expansion centre
+    offsets    : (s, d) stencil offsets from the expansion centre (d = 2 or 3)
     centre_pos : position of the expansion cell inside the stencil list
-    target     : (3,) offset of the evaluation point from the centre
+    target     : (d,) offset of the evaluation point from the centre
     """
     key = tuple(tuple(float(v) for v in row) for row in offsets)
     deriv_op, others = _derivative_operator(key, int(centre_pos), int(degree))
-    t = np.array([taylor_term(target, al) for al in taylor_exponents(degree)])
+    t = np.array([taylor_term(target, al) for al in taylor_exponents(degree, len(key[0]))])
     w_others = t @ deriv_op
     w = np.zeros(len(key))
     w[list(others)] = w_others

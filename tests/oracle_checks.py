@@ -92,7 +92,8 @@ def reproduction_error(oracle, scheme, p, k, o, s, rng, direction):
 def exact_pinned_fit(offsets, centre_pos, target, degree):
     """Unweighted least squares with the constant pinned, solved exactly via
     the normal equations over plain monomials (not the Taylor basis)."""
-    exps = [e for e in product(range(degree + 1), repeat=3) if 1 <= sum(e) <= degree]
+    dim = len(offsets[0])
+    exps = [e for e in product(range(degree + 1), repeat=dim) if 1 <= sum(e) <= degree]
     others = [q for q in range(len(offsets)) if q != centre_pos]
 
     def mono(d, e):
