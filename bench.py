@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--patch-faces", type=int, default=6003,
                     help="fine patches in the fused patch-halo leg, rounded up to a multiple "
                          "of 9 (0 disables it)")
+    ap.add_argument("--faces-2d", type=int, default=200000,
+                    help="two-dimensional faces in the 2D leg (0 disables it)")
     ap.add_argument("--no-reports", action="store_true",
                     help="skip the convergence and operator-build reports")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -317,6 +319,46 @@ def patches_leg(args, torch, api, wl):
             "alg_bytes": {"restrict_patches": rbytes, "interpolate_patches": ibytes}}
 
 
+def faces_2d_leg(args, torch, api, wl):
+    """Two-dimensional faces (p=9, k=3, U=59, FP64): the headline step's
+    launches (three schemes, restrict then interpolate) on 2D face buffers."""
+    import numpy as np
+
+    p, k, U = 9, 3, 59
+    b = wl.faces_2d(args.faces_2d, p, k, U, seed=wl.SEED_BASE + 7, device="cuda:0")
+    n = b.n
+    c_out, f_out = b.coarse.clone(), b.fine.clone()
+    d = (b.orientation, b.subface, b.coarse_offset, b.fine_offset)
+    launches, ops = [], {}
+    for scheme in (1, 2, 3):
+        rop = api.build_transfer_operator(api.FT_RESTRICT, scheme, p, k, api.FT_BUILD_2D)
+        iop = api.build_transfer_operator(api.FT_INTERPOLATE, scheme, p, k, api.FT_BUILD_2D)
+        ops[("restrict", scheme)], ops[("interpolate", scheme)] = rop, iop
+        launches.append((f"restrict_{SCHEME_NAMES[scheme]}",
+                         lambda rop=rop: api.restrict_faces(rop, *d, U, b.fine, c_out)))
+        launches.append((f"interpolate_{SCHEME_NAMES[scheme]}",
+                         lambda iop=iop: api.interpolate_faces(iop, *d, U, b.coarse, f_out)))
+    ms, kern = run_steps(launches, args.steps, args.warmup, torch)
+    o_np, s_np = b.orientation.cpu().numpy(), b.subface.cpu().numpy()
+    kernels = {}
+    for (direction, scheme), op in ops.items():
+        name = f"{direction}_{SCHEME_NAMES[scheme]}"
+        per = {}
+        for o in range(4):
+            for s_ in range(3):
+                rows, cols, vals = op.segment(o, s_)
+                per[(o, s_)] = (len(np.unique(cols[vals != 0])) + len(np.unique(rows))) * U * 8
+        counts = np.zeros((4, 3), dtype=np.int64)
+        np.add.at(counts, (o_np, s_np), 1)
+        nbytes = int(sum(per[(o, s_)] * counts[o, s_] for o in range(4) for s_ in range(3)))
+        kernels[name] = {"ms": round(kern[name], 4), "alg_bytes": nbytes,
+                         "GB/s": round(nbytes / (kern[name] * 1e-3) / 1e9, 1)}
+    produced = 3 * n * (3 * k * (p // 3) + k * (p // 3)) * U
+    return {"workload": f"{n} two-dimensional hanging faces, p=9, k=3, U=59, FP64; "
+                        "dlinear+taylor2+taylor3; restrict+interpolate",
+            "ms_per_step": ms, "value": produced / (ms * 1e-3), "kernels": kernels}
+
+
 def cpu_baseline(batch, n_faces, torch):
     """The FP64 oracle on the host, on the first n_faces faces of the same
     batch; operators are built before timing (the paper times repeated calls
@@ -473,6 +515,10 @@ def main():
     if args.mesh_meshes > 0:
         result["mesh"] = mesh_leg(args, torch, api, wl)
         progress("mesh leg done")
+
+    if args.faces_2d > 0:
+        result["faces_2d"] = faces_2d_leg(args, torch, api, wl)
+        progress("2D leg done")
 
     if args.patch_faces > 0:
         result["patches"] = patches_leg(args, torch, api, wl)

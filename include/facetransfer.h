@@ -120,6 +120,19 @@ extern "C" {
 /* Build flags. */
 #define FT_BUILD_HOST_ONLY 1 /* build the weight tables on the host only; the
                                 operator can be inspected but not applied  */
+#define FT_BUILD_2D 2        /* two-dimensional faces (see below)           */
+
+/* Two dimensions (Sections 2-3 state the method for any dimension): with
+ * FT_BUILD_2D the operator works on faces of two-dimensional patches (p^2
+ * cells, halo depth k).  Orientation o in 0..3 names the normal axis
+ * a = o mod 2; the tangential axis is the other one; the fine patch lies on
+ * the + side for o < 2.  A face buffer holds 2k cells along a and p along the
+ * tangential axis, cell (i0, i1) at cell number i1*e0 + i0 (axis 0 fastest,
+ * unknowns innermost), normal index [0, k) on the - side.  Subface s in 0..2
+ * covers coarse columns [s*p/3, (s+1)*p/3).  The stencils are the 3 x 3
+ * box (plus the two-away axial points for degree 3).  interpolate_faces and
+ * restrict_faces take such operators in every dtype; plans and the patch
+ * calls below take three-dimensional operators only. */
 
 typedef struct ft_operator ft_operator;
 
@@ -180,11 +193,13 @@ int restrict_faces(const ft_operator* op, int64_t n_faces, const int8_t* orienta
 
 /* Operator facts, written to info[0..n_info) (host memory):
  * [0] direction  [1] scheme  [2] p  [3] k
- * [4] rows per expansion cell (interpolation 9k, restriction k)
- * [5] expansion cells per subface ((p/3)^2)
+ * [4] rows per expansion cell (interpolation 9k, restriction k; 2D: 3k, k)
+ * [5] expansion cells per subface ((p/3)^2; 2D: p/3)
  * [6] number of distinct weight blocks  [7] largest block width (stencil)
- * [8] nonzero weights in one subface segment (orientation 0, subface 4)
+ * [8] nonzero weights in one subface segment (orientation 0, subface 4;
+ *     2D: subface 1)
  * [9] bytes of the float64 weight tables
+ * [10] dimension (3, or 2 with FT_BUILD_2D)
  * Errors: FT_ERR_INVALID for a null op / info or n_info < 1. */
 int transfer_operator_info(const ft_operator* op, int64_t* info, int n_info);
 

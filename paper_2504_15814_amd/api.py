@@ -17,6 +17,7 @@ FT_INTERPOLATE, FT_RESTRICT = 0, 1
 FT_DLINEAR, FT_TAYLOR2, FT_TAYLOR3 = 1, 2, 3
 FT_F64, FT_F32, FT_F32_BF16X3, FT_F32_BF16X6 = 0, 1, 2, 3
 FT_BUILD_HOST_ONLY = 1
+FT_BUILD_2D = 2
 FT_HALF_INNER, FT_HALF_OUTER, FT_HALF_BOTH = 1, 2, 3
 
 _DTYPES = {torch.float64: FT_F64, torch.float32: FT_F32}
@@ -48,10 +49,10 @@ class TransferOperator:
         return self._h
 
     def info(self):
-        buf = (ctypes.c_int64 * 10)()
-        _check(_lib.load().transfer_operator_info(self.handle, buf, 10), "transfer_operator_info")
+        buf = (ctypes.c_int64 * 11)()
+        _check(_lib.load().transfer_operator_info(self.handle, buf, 11), "transfer_operator_info")
         keys = ("direction", "scheme", "p", "k", "rows_per_anchor", "anchors", "blocks",
-                "max_width", "nnz_segment", "weight_bytes")
+                "max_width", "nnz_segment", "weight_bytes", "dim")
         return dict(zip(keys, list(buf)))
 
     def segment(self, orientation, subface):

@@ -107,6 +107,7 @@ int upload(ft_operator* op) {
   d.scheme = op->scheme;
   d.p = op->p;
   d.k = op->k;
+  d.dim = op->dim;
   d.R = op->R;
   d.E = op->E;
   d.copy_row = op->copy_row;
@@ -230,9 +231,10 @@ int build_transfer_operator(int direction, int scheme, int p, int k, int flags,
   if (k < 1 || k > 3) return fail(FT_ERR_UNSUPPORTED, "k must be 1, 2 or 3");
   if (k == 1 && scheme != FT_DLINEAR)
     return fail(FT_ERR_UNSUPPORTED, "k = 1 is supported by FT_DLINEAR only");
-  if (flags & ~FT_BUILD_HOST_ONLY) return fail(FT_ERR_INVALID, "unknown flags");
+  if (flags & ~(FT_BUILD_HOST_ONLY | FT_BUILD_2D)) return fail(FT_ERR_INVALID, "unknown flags");
   ft_operator* op = new (std::nothrow) ft_operator();
   if (!op) return fail(FT_ERR_NOMEM, "host allocation failed");
+  op->dim = (flags & FT_BUILD_2D) ? 2 : 3;
   op->direction = direction;
   op->scheme = scheme;
   op->p = p;
@@ -308,6 +310,8 @@ int interpolate_patches(const ft_operator* op, int64_t n_faces, const int8_t* or
                         int64_t coarse_elems, void* fine, int64_t fine_elems, void* stream) {
   int rc = check_apply(op, FT_INTERPOLATE, n_faces, orientation, subface, coarse_offset,
                        fine_offset, unknowns, dtype, coarse, coarse_elems, fine, fine_elems, true);
+  if (rc == FT_OK && op->dim != 3)
+    rc = fail(FT_ERR_UNSUPPORTED, "patch calls take three-dimensional operators");
   if (rc != FT_OK || n_faces == 0) return rc == FT_OK ? ok() : rc;
   ft::LaunchArgs la{n_faces, orientation, subface, coarse_offset, fine_offset, unknowns, dtype,
                     coarse, coarse_elems, fine, fine_elems, op->d_errors, ft::kPatches};
@@ -328,6 +332,8 @@ int restrict_patches(const ft_operator* op, int64_t n_faces, const int8_t* orien
   int rc = check_apply(op, FT_RESTRICT, n_faces, orientation, subface, fine_offset,
                        coarse_offset, unknowns, dtype, fine, fine_elems, coarse, coarse_elems,
                        true);
+  if (rc == FT_OK && op->dim != 3)
+    rc = fail(FT_ERR_UNSUPPORTED, "patch calls take three-dimensional operators");
   if (rc != FT_OK || n_faces == 0) return rc == FT_OK ? ok() : rc;
   ft::LaunchArgs la{n_faces, orientation, subface, fine_offset, coarse_offset, unknowns, dtype,
                     fine, fine_elems, coarse, coarse_elems, op->d_errors, ft::kPatches};
@@ -390,22 +396,25 @@ int transfer_operator_info(const ft_operator* op, int64_t* info, int n_info) {
     wbytes += (int64_t)op->blocks[c].weights.size() * 8;
   }
   int64_t nnz = 0;
+  const bool d3 = op->dim == 3;
   {
-    // Nonzero weights of the (orientation 0, subface 4) segment.
+    // Nonzero weights of the middle segment (orientation 0, subface 4; in 2D
+    // subface 1).
     const int E = op->E;
-    for (int ec = 0; ec < E; ++ec)
+    for (int ec = 0; ec < (d3 ? E : 1); ++ec)
       for (int eb = 0; eb < E; ++eb) {
         const int ab = op->direction == 0 ? E + eb : 3 * eb + 1;
         const int ac = op->direction == 0 ? E + ec : 3 * ec + 1;
-        const auto& blk = op->blocks[ft::axis_class(ab, op->p) * ft::kAxisClasses +
-                                     ft::axis_class(ac, op->p)];
-        for (double w : blk.weights) nnz += (w != 0.0);
+        const int cls = ft::axis_class(ab, op->p) * ft::kAxisClasses +
+                        (d3 ? ft::axis_class(ac, op->p) : 0);
+        for (double w : op->blocks[cls].weights) nnz += (w != 0.0);
       }
   }
-  const int64_t vals[10] = {op->direction, op->scheme, op->p, op->k, op->R,
-                            (int64_t)op->E * op->E, blocks, widest, nnz, wbytes};
-  for (int i = 0; i < n_info && i < 10; ++i) info[i] = vals[i];
-  for (int i = 10; i < n_info; ++i) info[i] = 0;
+  const int64_t vals[11] = {op->direction, op->scheme, op->p, op->k, op->R,
+                            d3 ? (int64_t)op->E * op->E : (int64_t)op->E, blocks, widest, nnz,
+                            wbytes, op->dim};
+  for (int i = 0; i < n_info && i < 11; ++i) info[i] = vals[i];
+  for (int i = 11; i < n_info; ++i) info[i] = 0;
   return ok();
 }
 
@@ -413,26 +422,29 @@ int transfer_operator_segment(const ft_operator* op, int orientation, int subfac
                               int64_t capacity, int64_t* rows, int64_t* cols, double* vals,
                               int64_t* n_entries) {
   if (!op || !n_entries) return fail(FT_ERR_INVALID, "NULL op or n_entries");
-  if (orientation < 0 || orientation > 5 || subface < 0 || subface > 8)
-    return fail(FT_ERR_INVALID, "orientation must be 0..5 and subface 0..8");
+  const bool d3 = op->dim == 3;
+  if (orientation < 0 || orientation > (d3 ? 5 : 3) || subface < 0 || subface > (d3 ? 8 : 2))
+    return fail(FT_ERR_INVALID, d3 ? "orientation must be 0..5 and subface 0..8"
+                                   : "orientation must be 0..3 and subface 0..2 (2D)");
   const int p = op->p, k = op->k, E = op->E, R = op->R;
-  const ft::FaceStrides st = ft::face_strides(orientation % 3, p, k);
+  const ft::FaceView st = d3 ? ft::buffer_view(orientation % 3, p, k)
+                             : ft::buffer_view2d(orientation % 2, p, k);
   int nbase, nsign;
-  ft::normal_map(op->direction, orientation, k, &nbase, &nsign);
-  const int sb = subface % 3, sc = subface / 3;
+  ft::normal_map_side(op->direction, orientation < (d3 ? 3 : 2), k, &nbase, &nsign);
+  const int sb = d3 ? subface % 3 : subface, sc = d3 ? subface / 3 : 0;
   std::vector<int64_t> rr, cc;
   std::vector<double> vv;
-  for (int ec = 0; ec < E; ++ec)
+  for (int ec = 0; ec < (d3 ? E : 1); ++ec)
     for (int eb = 0; eb < E; ++eb) {
       const int ab = op->direction == 0 ? sb * E + eb : 3 * eb + 1;
-      const int ac = op->direction == 0 ? sc * E + ec : 3 * ec + 1;
-      const auto& blk =
-          op->blocks[ft::axis_class(ab, p) * ft::kAxisClasses + ft::axis_class(ac, p)];
+      const int ac = d3 ? (op->direction == 0 ? sc * E + ec : 3 * ec + 1) : 0;
+      const auto& blk = op->blocks[ft::axis_class(ab, p) * ft::kAxisClasses +
+                                   (d3 ? ft::axis_class(ac, p) : 0)];
       const int anchor = ab * st.sb + ac * st.sc;
       for (int r = 0; r < R; ++r) {
         int dcell;
         if (op->direction == 0) {
-          const int g = r / 9, tb = (r / 3) % 3, tc = r % 3;
+          const int g = d3 ? r / 9 : r / 3, tb = d3 ? (r / 3) % 3 : r % 3, tc = d3 ? r % 3 : 0;
           dcell = (nbase + nsign * g) * st.sa + (3 * eb + tb) * st.sb + (3 * ec + tc) * st.sc;
         } else {
           dcell = (nbase + nsign * r) * st.sa + (sb * E + eb) * st.sb + (sc * E + ec) * st.sc;

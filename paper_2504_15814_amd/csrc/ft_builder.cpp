@@ -23,12 +23,18 @@ using Vec3 = std::array<long double, 3>;
 using Cell = std::tuple<int, int, int>;  // (n, b, c) in the reference frame
 using Row = std::map<Cell, long double>;
 
-// Monomial exponents with 1 <= |alpha| <= degree (the constant is pinned).
-std::vector<std::array<int, 3>> exponents(int degree) {
+// Monomial exponents with 1 <= |alpha| <= degree (the constant is pinned), in
+// `dim` variables (the third exponent is zero in two dimensions).
+std::vector<std::array<int, 3>> exponents(int degree, int dim) {
   std::vector<std::array<int, 3>> out;
   for (int t = 1; t <= degree; ++t)
-    for (int e0 = t; e0 >= 0; --e0)
+    for (int e0 = t; e0 >= 0; --e0) {
+      if (dim == 2) {
+        out.push_back({e0, t - e0, 0});
+        continue;
+      }
       for (int e1 = t - e0; e1 >= 0; --e1) out.push_back({e0, e1, t - e0 - e1});
+    }
   return out;
 }
 
@@ -43,10 +49,10 @@ long double monomial(const Vec3& d, const std::array<int, 3>& e) {
 // weight row over `offs` per target.  Householder QR of the (s-1) x n matrix
 // of monomials at the non-centre offsets; X = R^{-1} Q^T is the map from
 // (values - centre value) to the monomial coefficients.
-bool pinned_fit(const std::vector<Vec3>& offs, int centre, int degree,
+bool pinned_fit(const std::vector<Vec3>& offs, int centre, int degree, int dim,
                 const std::vector<Vec3>& targets, std::vector<std::vector<long double>>* W,
                 std::string* err) {
-  const auto ex = exponents(degree);
+  const auto ex = exponents(degree, dim);
   const int n = (int)ex.size();
   std::vector<int> others;
   for (int q = 0; q < (int)offs.size(); ++q)
@@ -121,16 +127,20 @@ void axis_box(int centre, int lo, int hi, int* box_mid) {
   *box_mid = std::min(std::max(centre, lo + 1), hi - 1);
 }
 
-std::vector<Cell> taylor_stencil(int degree, Cell centre, const int lo[3], const int hi[3]) {
+// In two dimensions the third coordinate is 0 and the box is 3 x 3.
+std::vector<Cell> taylor_stencil(int degree, int dim, Cell centre, const int lo[3],
+                                 const int hi[3]) {
   int mid[3];
   const int cc[3] = {std::get<0>(centre), std::get<1>(centre), std::get<2>(centre)};
-  for (int i = 0; i < 3; ++i) axis_box(cc[i], lo[i], hi[i], &mid[i]);
+  for (int i = 0; i < dim; ++i) axis_box(cc[i], lo[i], hi[i], &mid[i]);
+  if (dim == 2) mid[2] = 0;
+  const int r2 = dim == 3 ? 1 : 0;
   std::vector<Cell> pts;
   for (int d0 = -1; d0 <= 1; ++d0)
     for (int d1 = -1; d1 <= 1; ++d1)
-      for (int d2 = -1; d2 <= 1; ++d2) pts.emplace_back(mid[0] + d0, mid[1] + d1, mid[2] + d2);
+      for (int d2 = -r2; d2 <= r2; ++d2) pts.emplace_back(mid[0] + d0, mid[1] + d1, mid[2] + d2);
   if (degree >= 3) {
-    for (int ax = 0; ax < 3; ++ax)
+    for (int ax = 0; ax < dim; ++ax)
       for (int st = -2; st <= 2; st += 4) {
         int q[3] = {mid[0], mid[1], mid[2]};
         q[ax] += st;
@@ -142,9 +152,9 @@ std::vector<Cell> taylor_stencil(int degree, Cell centre, const int lo[3], const
 
 // Taylor rows about `centre` (reference cells, spacing `unit` per index)
 // evaluated at the given target offsets (in index units).
-bool taylor_rows(int degree, Cell centre, const int lo[3], const int hi[3],
+bool taylor_rows(int degree, int dim, Cell centre, const int lo[3], const int hi[3],
                  const std::vector<Vec3>& targets, std::vector<Row>* rows, std::string* err) {
-  const auto st = taylor_stencil(degree, centre, lo, hi);
+  const auto st = taylor_stencil(degree, dim, centre, lo, hi);
   std::vector<Vec3> offs;
   int ci = -1;
   for (size_t q = 0; q < st.size(); ++q) {
@@ -158,7 +168,7 @@ bool taylor_rows(int degree, Cell centre, const int lo[3], const int hi[3],
     return false;
   }
   std::vector<std::vector<long double>> W;
-  if (!pinned_fit(offs, ci, degree, targets, &W, err)) return false;
+  if (!pinned_fit(offs, ci, degree, dim, targets, &W, err)) return false;
   rows->clear();
   for (size_t t = 0; t < targets.size(); ++t) {
     Row r;
@@ -189,29 +199,32 @@ std::map<int, long double> linear_1d(long num, long den, int lo, int hi) {
   return w;
 }
 
-// Rows of one block (direction, scheme) for the anchor column (ab, ac).
+// Rows of one block (direction, scheme) for the anchor column (ab, ac); in two
+// dimensions ac = 0 and there is no third axis.
 bool block_rows(const ft_operator* op, int ab, int ac, std::vector<Row>* rows, std::string* err) {
-  const int p = op->p, k = op->k;
+  const int p = op->p, k = op->k, dim = op->dim;
   const int lo[3] = {-k, 0, 0};
-  const int hi[3] = {k - 1, p - 1, p - 1};
+  const int hi[3] = {k - 1, p - 1, dim == 3 ? p - 1 : 0};
+  const int tcn = dim == 3 ? 3 : 1;  // fine columns per coarse column along the third axis
   rows->clear();
   if (op->direction == 0) {
     // Interpolation: expansion cell = containing coarse cell (n = 0, ab, ac);
     // row (g, tb, tc) is the fine ghost centre at offset ((g-1)/3, (tb-1)/3,
-    // (tc-1)/3) coarse widths from it.
+    // (tc-1)/3) coarse widths from it (no tc in two dimensions).
     std::vector<Vec3> targets;
     for (int g = 0; g < k; ++g)
       for (int tb = 0; tb < 3; ++tb)
-        for (int tc = 0; tc < 3; ++tc)
+        for (int tc = 0; tc < tcn; ++tc)
           targets.push_back({(long double)(g - 1) / 3.0L, (long double)(tb - 1) / 3.0L,
-                             (long double)(tc - 1) / 3.0L});
+                             dim == 3 ? (long double)(tc - 1) / 3.0L : 0.0L});
     if (op->scheme == FT_DLINEAR) {
       for (int g = 0; g < k; ++g)
         for (int tb = 0; tb < 3; ++tb)
-          for (int tc = 0; tc < 3; ++tc) {
+          for (int tc = 0; tc < tcn; ++tc) {
             const auto wn = linear_1d(g - 1, 3, lo[0], hi[0]);
             const auto wb = linear_1d(3L * ab + tb - 1, 3, 0, p - 1);
-            const auto wc = linear_1d(3L * ac + tc - 1, 3, 0, p - 1);
+            std::map<int, long double> wc;
+            if (dim == 3) wc = linear_1d(3L * ac + tc - 1, 3, 0, p - 1); else wc[0] = 1.0L;
             Row r;
             for (auto& [i0, w0] : wn)
               for (auto& [i1, w1] : wb)
@@ -220,11 +233,13 @@ bool block_rows(const ft_operator* op, int ab, int ac, std::vector<Row>* rows, s
           }
       return true;
     }
-    return taylor_rows(op->scheme, Cell(0, ab, ac), lo, hi, targets, rows, err);
+    return taylor_rows(op->scheme, dim, Cell(0, ab, ac), lo, hi, targets, rows, err);
   }
   // Restriction: coarse target layer l (centre 3l + 3/2 fine widths into the
   // fine side); its nearest fine cell is layer min(3l+1, k-1) of the
-  // coincident column (ab, ac) = (3 mu + 1) along b and c.
+  // coincident column (ab, ac) = (3 mu + 1) along b (and c).
+  const int rc = dim == 3 ? 1 : 0;
+  const long double ncols = dim == 3 ? 9.0L : 3.0L;
   for (int l = 0; l < k; ++l) {
     const int eta = std::min(3 * l + 1, k - 1);
     if (op->scheme == FT_DLINEAR) {
@@ -239,12 +254,12 @@ bool block_rows(const ft_operator* op, int ab, int ac, std::vector<Row>* rows, s
       Row r;
       for (auto& [i0, w0] : wn)
         for (int db = -1; db <= 1; ++db)
-          for (int dc = -1; dc <= 1; ++dc) r[Cell(i0, ab + db, ac + dc)] += w0 / 9.0L;
+          for (int dc = -rc; dc <= rc; ++dc) r[Cell(i0, ab + db, ac + dc)] += w0 / ncols;
       rows->push_back(r);
     } else {
       std::vector<Row> one;
       const std::vector<Vec3> tgt = {{(long double)(3 * l + 1 - eta), 0.0L, 0.0L}};
-      if (!taylor_rows(op->scheme, Cell(eta, ab, ac), lo, hi, tgt, &one, err)) return false;
+      if (!taylor_rows(op->scheme, dim, Cell(eta, ab, ac), lo, hi, tgt, &one, err)) return false;
       rows->push_back(one[0]);
     }
   }
@@ -254,15 +269,15 @@ bool block_rows(const ft_operator* op, int ab, int ac, std::vector<Row>* rows, s
 }  // namespace
 
 std::string build_tables(ft_operator* op) {
-  const int p = op->p, k = op->k;
+  const int p = op->p, k = op->k, dim = op->dim;
   op->E = p / 3;
-  op->R = op->direction == 0 ? 9 * k : k;
+  op->R = op->direction == 0 ? (dim == 3 ? 9 : 3) * k : k;
   op->copy_row = -1;
   op->copy_n = 0;
   if (op->direction == 0) {
-    // (g, tb, tc) = (1, 1, 1): the coarse centre itself; with k = 1 no fine
-    // ghost centre coincides with a coarse one
-    op->copy_row = k >= 2 ? 13 : -1;
+    // (g, tb, tc) = (1, 1, 1) (3D) or (g, tb) = (1, 1) (2D): the coarse centre
+    // itself; with k = 1 no fine ghost centre coincides with a coarse one
+    op->copy_row = k >= 2 ? (dim == 3 ? 13 : 4) : -1;
     op->copy_n = 0;
   } else if (op->scheme != FT_DLINEAR) {
     op->copy_row = 0;  // layer 0 coincides with fine layer 1 (k >= 2)
@@ -276,12 +291,14 @@ std::string build_tables(ft_operator* op) {
     const int c = axis_class(m, p);
     if (rep[c] < 0) rep[c] = m;
   }
+  // Two dimensions: one class per anchor along b, stored at slot cb * 5.
   for (int cb = 0; cb < kAxisClasses; ++cb)
     for (int cc = 0; cc < kAxisClasses; ++cc) {
       HostBlock& blk = op->blocks[cb * kAxisClasses + cc];
       blk = HostBlock();
-      if (rep[cb] < 0 || rep[cc] < 0) continue;
-      const int ab = rep[cb], ac = rep[cc];
+      if (dim == 2 && cc != 0) continue;
+      if (rep[cb] < 0 || (dim == 3 && rep[cc] < 0)) continue;
+      const int ab = rep[cb], ac = dim == 3 ? rep[cc] : 0;
       std::vector<Row> rows;
       std::string err;
       if (!block_rows(op, ab, ac, &rows, &err)) return err;

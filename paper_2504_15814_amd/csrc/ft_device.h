@@ -48,7 +48,9 @@ __device__ __forceinline__ const FT_CONST P* cptr(const P* p) {
 // (src = fine, dst = coarse).  R rows per anchor; EC anchors per axis (0 = read
 // from the operator); COPY is the exact-copy row (its source is stencil entry
 // 0 of every block) or -1.  T storage, A accumulator, W weight type.
-template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W>
+// DIM 3, or 2 for two-dimensional faces (2k x p cells; no third axis, the
+// anchor index e runs over the p/3 coarse columns of the subface).
+template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W, int DIM = 3>
 __device__ __forceinline__ void apply_item(
     const DevOp* __restrict__ op_, const int face, const int e, const int layout,
     const int8_t* __restrict__ orientation_, const int8_t* __restrict__ subface_,
@@ -64,7 +66,7 @@ __device__ __forceinline__ void apply_item(
   constexpr int kGroup = 4;  // stencil loads in flight per wave before their FMAs
   const int lane = threadIdx.x & 63;
   const int E = EC > 0 ? EC : op->E;
-  const int eb = e % E, ec = e / E;
+  const int eb = DIM == 3 ? e % E : e, ec = DIM == 3 ? e / E : 0;
   const int p = op->p, k = op->k;
 
   const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
@@ -72,32 +74,36 @@ __device__ __forceinline__ void apply_item(
   // Elements one item may touch: a face buffer, or a whole patch box.
   const int P = p + 2 * k;
   const int64_t item_elems =
-      (layout == kFaceBuffers ? (int64_t)(2 * k * p * p) : (int64_t)P * P * P) * U;
+      (layout == kFaceBuffers ? (int64_t)(2 * k * p) * (DIM == 3 ? p : 1) : (int64_t)P * P * P) *
+      U;
   const int64_t so = src_offset[face];
   const int64_t dof = dst_offset[face];
-  const bool bad = o < 0 || o > 5 || s < 0 || s > 8 || so < 0 || dof < 0 ||
-                   so > src_elems - item_elems || dof > dst_elems - item_elems;
+  const bool bad = o < 0 || o > (DIM == 3 ? 5 : 3) || s < 0 || s > (DIM == 3 ? 8 : 2) || so < 0 ||
+                   dof < 0 || so > src_elems - item_elems || dof > dst_elems - item_elems;
   if (bad) {
     if (e == 0 && lane == 0) atomicAdd(errors, 1);
     return;
   }
   FaceView sv, dv;
-  transfer_views(DIR, layout, o, p, k, &sv, &dv);
+  if (DIM == 3)
+    transfer_views(DIR, layout, o, p, k, &sv, &dv);
+  else
+    sv = dv = buffer_view2d(o % 2, p, k);
   int nbase, nsign;
-  normal_map(DIR, o, k, &nbase, &nsign);
-  const int sb = s % 3, sc = s / 3;
+  normal_map_side(DIR, o < (DIM == 3 ? 3 : 2), k, &nbase, &nsign);
+  const int sb = DIM == 3 ? s % 3 : s, sc = DIM == 3 ? s / 3 : 0;
 
   // Anchor column in the source face and the block that serves it.
   const int anc_b = DIR == 0 ? sb * E + eb : 3 * eb + 1;
-  const int anc_c = DIR == 0 ? sc * E + ec : 3 * ec + 1;
-  const int cls = axis_class(anc_b, p) * kAxisClasses + axis_class(anc_c, p);
+  const int anc_c = DIM == 3 ? (DIR == 0 ? sc * E + ec : 3 * ec + 1) : 0;
+  const int cls = axis_class(anc_b, p) * kAxisClasses + (DIM == 3 ? axis_class(anc_c, p) : 0);
   const int width = op->width[cls];
   const int start = op->start[cls];
   const int anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
   const int nstride = nsign * sv.sa;
   // First destination cell of this anchor and the strides of its rows.
   const int dst_b = DIR == 0 ? 3 * eb : sb * E + eb;
-  const int dst_c = DIR == 0 ? 3 * ec : sc * E + ec;
+  const int dst_c = DIM == 3 ? (DIR == 0 ? 3 * ec : sc * E + ec) : 0;
   const int dst_cell0 = dv.base + nbase * dv.sa + dst_b * dv.sb + dst_c * dv.sc;
   const int dstride = nsign * dv.sa;
 
@@ -149,7 +155,8 @@ __device__ __forceinline__ void apply_item(
     for (int r = 0; r < R; ++r) {
       int dcell;
       if (DIR == 0) {
-        const int g = r / 9, tb = (r / 3) % 3, tc = r % 3;
+        const int g = DIM == 3 ? r / 9 : r / 3, tb = DIM == 3 ? (r / 3) % 3 : r % 3;
+        const int tc = DIM == 3 ? r % 3 : 0;
         dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
       } else {
         dcell = dst_cell0 + r * dstride;
@@ -164,7 +171,7 @@ __device__ __forceinline__ void apply_item(
 
 // Float32 interpolation on the matrix cores (see the file comment).
 // tile_all: the block's LDS transpose tiles, one per wave (wave_slot < 4).
-template <int R, int EC, int TERMS>
+template <int R, int EC, int TERMS, int DIM = 3>
 __device__ __forceinline__ void mfma_item(
     const DevOp* __restrict__ op_, const int face, const int e, const int layout,
     const int wave_slot, float (*tile_all)[32][65], const int8_t* __restrict__ orientation_,
@@ -177,37 +184,41 @@ __device__ __forceinline__ void mfma_item(
   const FT_CONST int8_t* subface = cptr(subface_);
   const FT_CONST int64_t* src_offset = cptr(src_offset_);
   const FT_CONST int64_t* dst_offset = cptr(dst_offset_);
-  // Row (g, tb, tc) = (1, 1, 1) is the coarse centre itself when k >= 2 (R >= 18);
-  // with k = 1 (R = 9) no row is a copy.
-  constexpr int COPY = R >= 18 ? 13 : -1;
+  // Row (g, tb, tc) = (1, 1, 1) (3D, R >= 18) or (g, tb) = (1, 1) (2D, R >= 6) is
+  // the coarse centre itself when k >= 2; with k = 1 no row is a copy.
+  constexpr int COPY = DIM == 3 ? (R >= 18 ? 13 : -1) : (R >= 6 ? 4 : -1);
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, col = lane & 31;
   const int E = EC > 0 ? EC : op->E;
-  const int eb = e % E, ec = e / E;
+  const int eb = DIM == 3 ? e % E : e, ec = DIM == 3 ? e / E : 0;
   const int p = op->p, k = op->k;
 
   const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
   const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
   const int P = p + 2 * k;
   const int64_t item_elems =
-      (layout == kFaceBuffers ? (int64_t)(2 * k * p * p) : (int64_t)P * P * P) * U;
+      (layout == kFaceBuffers ? (int64_t)(2 * k * p) * (DIM == 3 ? p : 1) : (int64_t)P * P * P) *
+      U;
   const int64_t so = src_offset[face];
   const int64_t dof = dst_offset[face];
-  const bool bad = o < 0 || o > 5 || s < 0 || s > 8 || so < 0 || dof < 0 ||
-                   so > src_elems - item_elems || dof > dst_elems - item_elems;
+  const bool bad = o < 0 || o > (DIM == 3 ? 5 : 3) || s < 0 || s > (DIM == 3 ? 8 : 2) || so < 0 ||
+                   dof < 0 || so > src_elems - item_elems || dof > dst_elems - item_elems;
   if (bad) {
     if (e == 0 && lane == 0) atomicAdd(errors, 1);
     return;
   }
   FaceView sv, dv;
-  transfer_views(0, layout, o, p, k, &sv, &dv);
+  if (DIM == 3)
+    transfer_views(0, layout, o, p, k, &sv, &dv);
+  else
+    sv = dv = buffer_view2d(o % 2, p, k);
   int nbase, nsign;
-  normal_map(0, o, k, &nbase, &nsign);
+  normal_map_side(0, o < (DIM == 3 ? 3 : 2), k, &nbase, &nsign);
   const int nstride = nsign * sv.sa;
   const int dstride = nsign * dv.sa;
-  const int sb = s % 3, sc = s / 3;
-  const int anc_b = sb * E + eb, anc_c = sc * E + ec;
-  const int cls = axis_class(anc_b, p) * kAxisClasses + axis_class(anc_c, p);
+  const int sb = DIM == 3 ? s % 3 : s, sc = DIM == 3 ? s / 3 : 0;
+  const int anc_b = sb * E + eb, anc_c = DIM == 3 ? sc * E + ec : 0;
+  const int cls = axis_class(anc_b, p) * kAxisClasses + (DIM == 3 ? axis_class(anc_c, p) : 0);
   const int width = op->width[cls];
   const int start = op->start[cls];
   const int nsteps = (width + kMfmaK - 1) / kMfmaK;
@@ -311,7 +322,8 @@ __device__ __forceinline__ void mfma_item(
       const float xc = COPY >= 0 ? sp[(int64_t)copy_cell * U + u] : 0.0f;
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const int g = m / 9, tb = (m / 3) % 3, tc = m % 3;
+        const int g = DIM == 3 ? m / 9 : m / 3, tb = DIM == 3 ? (m / 3) % 3 : m % 3;
+        const int tc = DIM == 3 ? m % 3 : 0;
         const int dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
         __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
       }

@@ -80,6 +80,12 @@ __host__ __device__ inline FaceView patch_view(int face, int p, int k) {
   return v;
 }
 
+// A two-dimensional face buffer (normal axis a of two): 2k cells along a and
+// p along the other axis, axis 0 fastest; the third stride is unused.
+__host__ __device__ inline FaceView buffer_view2d(int a, int p, int k) {
+  return a == 0 ? FaceView{1, 2 * k, 0, 0} : FaceView{p, 1, 0, 0};
+}
+
 // Layout of the arrays a transfer call reads and writes.
 enum Layout { kFaceBuffers = 0, kPatches = 1 };
 
@@ -101,11 +107,15 @@ __host__ __device__ inline void transfer_views(int direction, int layout, int o,
 // Interpolation: n counts into the coarse side, which is the - side (buffer
 // indices k-1, k-2, ...) when the fine patch lies on the + side (o < 3).
 // Restriction: n counts into the fine side.
-__host__ __device__ inline void normal_map(int direction, int o, int k, int* base, int* sign) {
-  const bool fine_plus = o < 3;
+__host__ __device__ inline void normal_map_side(int direction, bool fine_plus, int k, int* base,
+                                                int* sign) {
   const bool count_minus = (direction == 0) ? fine_plus : !fine_plus;
   *base = count_minus ? k - 1 : k;
   *sign = count_minus ? -1 : 1;
+}
+// Three dimensions: the fine patch is on the + side for o < 3 (o < 2 in 2D).
+__host__ __device__ inline void normal_map(int direction, int o, int k, int* base, int* sign) {
+  normal_map_side(direction, o < 3, k, base, sign);
 }
 
 // Packed stencil entry: normal coordinate (absolute) and tangential offsets
@@ -122,6 +132,7 @@ __host__ __device__ inline void unpack_point(int v, int* n, int* db, int* dc) {
 // Kernel-side view of an operator (passed by value as a kernel argument).
 struct DevOp {
   int direction, scheme, p, k;
+  int dim;        // 3, or 2 for two-dimensional faces
   int R;          // rows per expansion cell
   int E;          // expansion cells per axis and subface (p / 3)
   int copy_row;   // row that is an exact copy of a source cell, or -1
@@ -159,6 +170,7 @@ struct HostBlock {
 
 struct ft_operator {
   int direction, scheme, p, k, R, E, copy_row, copy_n;
+  int dim = 3;
   ft::HostBlock blocks[ft::kClasses];
   bool on_device = false;
   int device = -1;

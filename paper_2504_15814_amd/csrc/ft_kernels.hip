@@ -33,7 +33,7 @@ __device__ inline int64_t logical_block(int xcd_remap) {
   return (b % 8) * per + b / 8;
 }
 
-template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W>
+template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W, int DIM>
 __global__ __launch_bounds__(256) void apply_kernel(
     const DevOp* __restrict__ op, const Geometry geo, const int8_t* __restrict__ orientation,
     const int8_t* __restrict__ subface, const int64_t* __restrict__ src_offset,
@@ -42,20 +42,20 @@ __global__ __launch_bounds__(256) void apply_kernel(
     const W* __restrict__ weights, int* __restrict__ errors) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int E = EC > 0 ? EC : op->E;
-  const int anchors = E * E;
+  const int anchors = DIM == 3 ? E * E : E;
   // Launches are split on the host so that items fit in 31 bits.
   const int item = (int)logical_block(geo.xcd_remap) * geo.waves_per_block + wave;
   const int face = item / anchors;
   if (face >= geo.n_faces) return;
-  apply_item<DIR, R, EC, COPY, T, A, W>(op, face, item - face * anchors, geo.layout, orientation,
+  apply_item<DIR, R, EC, COPY, T, A, W, DIM>(op, face, item - face * anchors, geo.layout, orientation,
                                         subface, src_offset, dst_offset, U, src, src_elems, dst,
                                         dst_elems, weights, errors);
 }
 
-template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W>
+template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W, int DIM = 3>
 static hipError_t launch_one(const ft_operator* op, const Geometry& g0, const LaunchArgs& la,
                              const W* weights, hipStream_t stream) {
-  const int anchors = op->E * op->E;
+  const int anchors = DIM == 3 ? op->E * op->E : op->E;
   // Split so that (faces in a launch) x anchors stays below 2^30.
   const int64_t chunk = ((int64_t)1 << 30) / anchors;
   for (int64_t f0 = 0; f0 < la.n_faces; f0 += chunk) {
@@ -63,7 +63,7 @@ static hipError_t launch_one(const ft_operator* op, const Geometry& g0, const La
     g.n_faces = std::min<int64_t>(chunk, la.n_faces - f0);
     const int64_t items = g.n_faces * anchors;
     const int64_t blocks = (items + g.waves_per_block - 1) / g.waves_per_block;
-    hipLaunchKernelGGL((apply_kernel<DIR, R, EC, COPY, T, A, W>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((apply_kernel<DIR, R, EC, COPY, T, A, W, DIM>), dim3((unsigned)blocks),
                        dim3(64 * g.waves_per_block), 0, stream, op->d_devop, g, la.orientation + f0,
                        la.subface + f0, la.src_offset + f0, la.dst_offset + f0, la.U,
                        static_cast<const T*>(la.src), la.src_elems, static_cast<T*>(la.dst),
@@ -94,6 +94,22 @@ static hipError_t launch_typed(const ft_operator* op, const Geometry& g, const L
   // that precision; restriction sums always run in float64.
   const IA* iw;
   if constexpr (sizeof(IA) == 8) iw = d.w64; else iw = d.w32;
+  if (op->dim == 2) {
+    // Two-dimensional faces: 3k rows per interpolation anchor, k per
+    // restriction anchor; the anchor count is read from the operator.
+    const bool inject = op->copy_row == 0;
+    if (op->direction == FT_INTERPOLATE) {
+      if (op->k == 1) return launch_one<0, 3, 0, -1, T, IA, IA, 2>(op, g, la, iw, stream);
+      if (op->k == 2) return launch_one<0, 6, 0, 4, T, IA, IA, 2>(op, g, la, iw, stream);
+      return launch_one<0, 9, 0, 4, T, IA, IA, 2>(op, g, la, iw, stream);
+    }
+    if (op->k == 1) return launch_one<1, 1, 0, -1, T, double, double, 2>(op, g, la, d.w64, stream);
+    if (op->k == 2)
+      return inject ? launch_one<1, 2, 0, 0, T, double, double, 2>(op, g, la, d.w64, stream)
+                    : launch_one<1, 2, 0, -1, T, double, double, 2>(op, g, la, d.w64, stream);
+    return inject ? launch_one<1, 3, 0, 0, T, double, double, 2>(op, g, la, d.w64, stream)
+                  : launch_one<1, 3, 0, -1, T, double, double, 2>(op, g, la, d.w64, stream);
+  }
   if (op->direction == FT_INTERPOLATE) {
     if (op->k == 1) return launch_e<0, 9, -1, T, IA, IA>(op, g, la, iw, stream);
     if (op->k == 2) return launch_e<0, 18, 13, T, IA, IA>(op, g, la, iw, stream);
@@ -114,7 +130,7 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
   if (cfg.waves_per_block < 1 || cfg.waves_per_block > 4) return hipErrorInvalidValue;
   Geometry g;
   g.n_faces = la.n_faces;
-  g.anchors = op->E * op->E;
+  g.anchors = op->dim == 3 ? op->E * op->E : op->E;
   g.waves_per_block = cfg.waves_per_block;
   g.xcd_remap = cfg.xcd_remap;
   g.layout = la.layout;

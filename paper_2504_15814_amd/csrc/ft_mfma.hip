@@ -11,7 +11,7 @@
 
 namespace ft {
 
-template <int R, int EC, int TERMS>
+template <int R, int EC, int TERMS, int DIM>
 __global__ __launch_bounds__(256) void interp_mfma_kernel(
     const DevOp* __restrict__ op, const int64_t n_faces, const int waves_per_block,
     const int8_t* __restrict__ orientation, const int8_t* __restrict__ subface,
@@ -21,24 +21,24 @@ __global__ __launch_bounds__(256) void interp_mfma_kernel(
   __shared__ float tile_all[4][32][65];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int E = EC > 0 ? EC : op->E;
-  const int anchors = E * E;
+  const int anchors = DIM == 3 ? E * E : E;
   const int item = (int)blockIdx.x * waves_per_block + wave;
   const int face = item / anchors;
   if (face >= n_faces) return;
-  mfma_item<R, EC, TERMS>(op, face, item - face * anchors, layout, wave, tile_all, orientation,
+  mfma_item<R, EC, TERMS, DIM>(op, face, item - face * anchors, layout, wave, tile_all, orientation,
                           subface, src_offset, dst_offset, U, src, src_elems, dst, dst_elems,
                           errors);
 }
 
-template <int R, int EC, int TERMS>
+template <int R, int EC, int TERMS, int DIM = 3>
 static hipError_t launch_mfma_one(const ft_operator* op, const LaunchArgs& la,
                                   const LaunchConfig& cfg, hipStream_t stream) {
-  const int anchors = op->E * op->E;
+  const int anchors = DIM == 3 ? op->E * op->E : op->E;
   const int64_t chunk = ((int64_t)1 << 30) / anchors;
   for (int64_t f0 = 0; f0 < la.n_faces; f0 += chunk) {
     const int64_t nf = std::min<int64_t>(chunk, la.n_faces - f0);
     const int64_t blocks = (nf * anchors + cfg.waves_per_block - 1) / cfg.waves_per_block;
-    hipLaunchKernelGGL((interp_mfma_kernel<R, EC, TERMS>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((interp_mfma_kernel<R, EC, TERMS, DIM>), dim3((unsigned)blocks),
                        dim3(64 * cfg.waves_per_block), 0, stream, op->d_devop, nf,
                        cfg.waves_per_block, la.orientation + f0, la.subface + f0,
                        la.src_offset + f0, la.dst_offset + f0, la.U,
@@ -64,6 +64,17 @@ static hipError_t launch_mfma_e(const ft_operator* op, const LaunchArgs& la,
 hipError_t launch_interp_mfma(const ft_operator* op, const LaunchArgs& la,
                               const LaunchConfig& cfg, int terms, hipStream_t stream) {
   if (cfg.waves_per_block < 1 || cfg.waves_per_block > 4) return hipErrorInvalidValue;
+  if (op->dim == 2) {
+    const bool six = terms == 6;
+    if (op->k == 1)
+      return six ? launch_mfma_one<3, 0, 6, 2>(op, la, cfg, stream)
+                 : launch_mfma_one<3, 0, 3, 2>(op, la, cfg, stream);
+    if (op->k == 2)
+      return six ? launch_mfma_one<6, 0, 6, 2>(op, la, cfg, stream)
+                 : launch_mfma_one<6, 0, 3, 2>(op, la, cfg, stream);
+    return six ? launch_mfma_one<9, 0, 6, 2>(op, la, cfg, stream)
+               : launch_mfma_one<9, 0, 3, 2>(op, la, cfg, stream);
+  }
   if (op->k == 1)
     return terms == 6 ? launch_mfma_e<9, 6>(op, la, cfg, stream)
                       : launch_mfma_e<9, 3>(op, la, cfg, stream);

@@ -348,6 +348,7 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
     if (!b.op || b.n_faces < 0) return pfail(FT_ERR_INVALID, "batch with NULL op or n_faces < 0");
     if (!b.op->on_device || b.op->device != dev)
       return pfail(FT_ERR_INVALID, "batch operator is host-only or on another device");
+    if (b.op->dim != 3) return pfail(FT_ERR_UNSUPPORTED, "plans take three-dimensional operators");
     if (b.n_faces > 0 && (!b.orientation || !b.subface || !b.coarse_offset || !b.fine_offset))
       return pfail(FT_ERR_INVALID, "batch with NULL descriptor arrays");
     if (b.n_faces * (int64_t)b.op->E * b.op->E >= ((int64_t)1 << 31))

@@ -606,3 +606,24 @@ def patch_transitions(n_faces, p, k, U, seed, device="cpu", dtype=torch.float64,
     fine = torch.randn(n_faces * P3U, generator=dgen, dtype=dtype, device=device)
     return PatchTransitions(p, k, U, orientation.to(device), subface.to(device),
                             coarse_offset.to(device), fine_offset.to(device), coarse, fine)
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional faces
+# ---------------------------------------------------------------------------
+def faces_2d(n_faces, p, k, U, seed, device="cpu", dtype=torch.float64):
+    """Independent two-dimensional hanging faces (buffers of 2k x p cells,
+    axis 0 fastest, unknowns innermost), orientation uniform in 0..3 and
+    subface in 0..2 (CPU generator seeded `seed`), every stored value standard
+    normal (a generator of `device` seeded `seed`).  Returned as a FaceBatch
+    whose buffers each hold 2k p U elements."""
+    gen = torch.Generator().manual_seed(seed)
+    orient = torch.randint(0, 4, (n_faces,), generator=gen).to(torch.int8)
+    sub = torch.randint(0, 3, (n_faces,), generator=gen).to(torch.int8)
+    elems = 2 * k * p * U
+    offs = torch.arange(n_faces, dtype=torch.int64) * elems
+    dgen = torch.Generator(device=device).manual_seed(seed)
+    coarse = torch.randn(n_faces * elems, generator=dgen, dtype=dtype, device=device)
+    fine = torch.randn(n_faces * elems, generator=dgen, dtype=dtype, device=device)
+    return FaceBatch(p, k, U, orient.to(device), sub.to(device), offs.to(device), offs.clone().to(device),
+                     coarse, fine)

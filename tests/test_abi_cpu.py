@@ -235,3 +235,39 @@ def test_k1_only_for_dlinear():
     assert info["rows_per_anchor"] == 9 and info["k"] == 1
     rop = api.build_transfer_operator(1, 1, 9, 1, api.FT_BUILD_HOST_ONLY)
     assert rop.info()["rows_per_anchor"] == 1
+
+
+# Two-dimensional operators (FT_BUILD_2D) against the two-dimensional oracle.
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("scheme,p,k", [(s, p, k) for s in (1, 2, 3) for p in (6, 9, 12) for k in (2, 3)]
+                         + [(1, p, 1) for p in (6, 9, 12)])
+def test_library_2d_segments_equal_oracle(direction, scheme, p, k):
+    op = api.build_transfer_operator(direction, scheme, p, k, api.FT_BUILD_HOST_ONLY | api.FT_BUILD_2D)
+    ncell = 2 * k * p
+    for o, s in product(range(4), range(3)):
+        rows_l, cols_l, vals_l = op.segment(o, s)
+        D = np.zeros((ncell, ncell))
+        np.add.at(D, (rows_l, cols_l), vals_l)
+        rows, W = oracle.transfer2d.transfer_operator(direction, scheme, p, k, o, s)
+        assert set(rows_l.tolist()) == set(rows.tolist())
+        got = D[rows]
+        scale = np.abs(W).sum(axis=1)
+        assert (np.abs(got - W).max(axis=1) / scale).max() < 1e-13, (o, s)
+        big = np.abs(W) > 1e-12 * scale[:, None]
+        assert np.all(got[big] != 0.0)
+
+
+def test_2d_info_and_ranges():
+    op = api.build_transfer_operator(0, 3, 9, 3, api.FT_BUILD_HOST_ONLY | api.FT_BUILD_2D)
+    info = op.info()
+    assert info["dim"] == 2 and info["rows_per_anchor"] == 9 and info["anchors"] == 3
+    assert info["blocks"] == 5
+    assert api.build_transfer_operator(0, 3, 9, 3, api.FT_BUILD_HOST_ONLY).info()["dim"] == 3
+    lib = _lib.load()
+    n = ctypes.c_int64()
+    assert lib.transfer_operator_segment(op.handle, 4, 0, 0, None, None, None, ctypes.byref(n)) == api.FT_ERR_INVALID
+    assert lib.transfer_operator_segment(op.handle, 0, 3, 0, None, None, None, ctypes.byref(n)) == api.FT_ERR_INVALID
+    h = ctypes.c_void_p()
+    assert lib.build_transfer_operator(0, 2, 9, 1, api.FT_BUILD_HOST_ONLY | api.FT_BUILD_2D, ctypes.byref(h)) == api.FT_ERR_UNSUPPORTED
