@@ -24,6 +24,7 @@ Workloads (all seeds are 15814 + workload number; draw order is fixed below):
 5  three seeded 3-level AMR meshes (see workload5).
 6  hanging faces between patches with halos (see patch_transitions): 6,003
    fine patches of 9^3 cells, nine per coarse face, k = 3, U = 59.
+7  two-dimensional faces (see faces_2d): 200,000 faces, p = 9, k = 3, U = 59.
 Faces sit on a grid of 9^3 coarse patches (h_c = 1/81, h_f = 1/243).
 """
 
