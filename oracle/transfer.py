@@ -19,6 +19,15 @@ centre gives an injection, the others are extrapolations.
 d-linear baseline (Section 2, tensor product P = Px Py Pz): 1D linear weights
 per axis, multiplied; its restriction averages the covering fine cells.
 
+Patch sizes that are not multiples of 3 (Section 5.3 times them): fine and
+coarse cells do not align at the subface boundaries.  Every fine centre
+still lies inside one coarse cell, at offset -1/3, 0 or 1/3 of a coarse width
+from its centre, and every coarse centre lies on exactly one fine face, on a
+fine centre; a fine face restricts into the coarse columns whose centres it
+holds.  Where such a column straddles two fine faces, the averaging
+restriction takes the fine column through its centre instead of the mean of
+three.
+
 Operators are dense float64 matrices W (rows = destination cells, columns = all
 2k p^2 cells of the source face buffer) with the destination cell numbers.
 """
@@ -38,8 +47,8 @@ INTERPOLATE, RESTRICT = 0, 1
 def _check(scheme, p, k, o, s):
     if scheme not in (DLINEAR, TAYLOR2, TAYLOR3):
         raise ValueError(f"unknown scheme {scheme}")
-    if p < 6 or p % 3:
-        raise ValueError(f"p must be a multiple of 3 and >= 6, got {p}")
+    if p < 6:
+        raise ValueError(f"p must be >= 6, got {p}")
     if k not in (1, 2, 3):
         raise ValueError(f"k must be 1, 2 or 3, got {k}")
     if k == 1 and scheme != DLINEAR:
@@ -114,8 +123,15 @@ def _dlinear_restriction_row(o, p, k, s, target_pos, fine_pos, ext):
     tang = {}
     for ax in (b, c):
         lo = target_pos[ax] - 1.5
-        tang[ax] = [i for i in range(ext[ax]) if lo < fine_pos[ax][i] < lo + 3.0]
-        assert len(tang[ax]) == 3
+        under = [i for i in range(ext[ax]) if lo < fine_pos[ax][i] < lo + 3.0]
+        if len(under) == 3:
+            tang[ax] = {i: 1.0 / 3.0 for i in under}
+        else:
+            # p not a multiple of 3: the coarse column straddles two fine
+            # faces; this face holds the fine column through its centre
+            hit = [i for i in under if fine_pos[ax][i] == target_pos[ax]]
+            assert len(hit) == 1
+            tang[ax] = {hit[0]: 1.0}
     layers = sorted(range(ext[a]), key=lambda i: side * fine_pos[a][i])
     inner = [i for i in layers if side * fine_pos[a][i] > 0]
     covered = [i for i in inner if abs(side * fine_pos[a][i] - depth_T) < 1.5]
@@ -128,11 +144,11 @@ def _dlinear_restriction_row(o, p, k, s, target_pos, fine_pos, ext):
         normal = {i1: 1.0 - t, i2: t}
     row = np.zeros(geo.cell_count(p, k))
     for ia, wa in normal.items():
-        for ib in tang[b]:
-            for ic in tang[c]:
+        for ib, wb in tang[b].items():
+            for ic, wc in tang[c].items():
                 idx = [0, 0, 0]
                 idx[a], idx[b], idx[c] = ia, ib, ic
-                row[geo.cell_index(ext, idx)] += wa / 9.0
+                row[geo.cell_index(ext, idx)] += wa * wb * wc
     return row
 
 
@@ -156,11 +172,12 @@ def restriction_operator(scheme, p, k, o, s):
     for tc in cells:
         if not geo.coarse_fine_side_half(o, k, tc):
             continue
-        if not (sb * (p // 3) <= tc[b] < (sb + 1) * (p // 3)):
-            continue
-        if not (sc * (p // 3) <= tc[c] < (sc + 1) * (p // 3)):
-            continue
         XT = geo.coarse_position(o, p, k, tc)
+        # the coarse columns whose centre lies on this fine face (with p not a
+        # multiple of 3 a coarse column straddles two fine faces; its centre
+        # never lies on their boundary)
+        if not (sb * p <= XT[b] < (sb + 1) * p and sc * p <= XT[c] < (sc + 1) * p):
+            continue
         if scheme == DLINEAR:
             row = _dlinear_restriction_row(o, p, k, s, XT, per_axis_pos, ext)
         else:

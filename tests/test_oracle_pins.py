@@ -308,3 +308,98 @@ def test_restriction_segments_tile_k1():
             rows, _ = oracle.restriction_operator(1, p, 1, o, s)
             seen.extend(rows.tolist())
         assert len(seen) == len(set(seen)) == p * p
+
+
+# Patch sizes that are not multiples of 3 (Section 5.3 times them; fine and
+# coarse cells do not align at the subface boundaries).
+
+GENERAL_P = [(7, 2), (8, 3), (10, 2), (10, 3)]
+
+
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+@pytest.mark.parametrize("p,k", GENERAL_P)
+@pytest.mark.parametrize("direction", [0, 1])
+def test_general_p_reproduction(scheme, p, k, direction):
+    rng = np.random.default_rng(3000 + 100 * scheme + 10 * p + k + direction)
+    worst = 0.0
+    for o in range(6):
+        for s in (0, 1, 2, 4, 5, 8):
+            worst = max(worst, chk.reproduction_error(oracle, scheme, p, k, o, s, rng, direction))
+    assert worst < 1e-12, worst
+
+
+@pytest.mark.parametrize("p", [7, 8, 10])
+def test_general_p_rows_copies_and_tiling(p):
+    for k in (1, 2, 3):
+        schemes = (1,) if k == 1 else (1, 2, 3)
+        for scheme, o in product(schemes, (0, 4)):
+            seen = []
+            for s in range(9):
+                rows, W = oracle.restriction_operator(scheme, p, k, o, s)
+                assert np.allclose(W.sum(axis=1), 1.0, atol=1e-13)
+                seen.extend(rows.tolist())
+                irows, IW = oracle.interpolation_operator(scheme, p, k, o, s)
+                assert len(irows) == k * p * p and np.allclose(IW.sum(axis=1), 1.0, atol=1e-13)
+                # coinciding centres are copies, bit for bit
+                fpos = chk.fine_centres(o, p, k, s)[irows]
+                cpos = chk.coarse_centres(o, p, k)
+                for r in range(len(irows)):
+                    hit = np.flatnonzero(np.all(cpos == fpos[r], axis=1))
+                    if len(hit):
+                        want = np.zeros(IW.shape[1])
+                        want[hit[0]] = 1.0
+                        assert np.array_equal(IW[r], want)
+            # the nine fine faces restrict into disjoint columns covering the half
+            assert len(seen) == len(set(seen)) == k * p * p
+
+
+def test_general_p_restriction_columns_fixture():
+    cases = []
+    with open(chk.os.path.join(chk.GOLDEN, "general_p_columns.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                p, sb, m, *pairs = line.split()
+                w = {int(a): float(Fraction(b)) for a, b in (x.split(":") for x in pairs)}
+                cases.append((int(p), int(sb), int(m), w))
+    assert len(cases) == 15
+    k, o = 2, 0  # x-normal face: b = axis 1, c = axis 2; fine on the + side
+    for p, sb, m, want in cases:
+        mc = {7: 3, 8: 3}[p]  # a coarse column of the middle row sc = 1 with three fine columns
+        rows, W = oracle.restriction_operator(1, p, k, o, sb + 3)
+        a, ext, idx = chk.buffer_grid(o, p, k)
+        r = [i for i, cell in enumerate(rows) if tuple(idx[cell]) == (k, m, mc)]
+        assert len(r) == 1, (p, sb, m)
+        wb = np.zeros(p)
+        np.add.at(wb, idx[:, 1], W[r[0]])
+        got = {j: wb[j] for j in range(p) if wb[j] != 0.0}
+        assert set(got) == set(want), (p, sb, m, got)
+        for j, v in want.items():
+            assert got[j] == pytest.approx(v, abs=1e-15)
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("scheme", [2, 3])
+def test_general_p_exact_rational(direction, scheme):
+    """Brute force on p = 7 faces: every Taylor row from exact arithmetic."""
+    p, k = 7, 2
+    for o, s in ((0, 1), (5, 7)):
+        rows, W = oracle.transfer_operator(direction, scheme, p, k, o, s)
+        a, ext, idx = chk.buffer_grid(o, p, k)
+        src_pos = chk.coarse_centres(o, p, k) if direction == 0 else chk.fine_centres(o, p, k, s)
+        dst_pos = chk.fine_centres(o, p, k, s) if direction == 0 else chk.coarse_centres(o, p, k)
+        unit = 3.0 if direction == 0 else 1.0
+        for r, dst in enumerate(rows):
+            X = dst_pos[dst]
+            if direction == 0:
+                home = int(np.flatnonzero(np.abs(src_pos - X).max(axis=1) < 1.5)[0])
+            else:
+                home = int(np.argmin(((src_pos - X) ** 2).sum(axis=1)))
+            stencil = oracle.taylor_stencil(tuple(idx[home]), ext, scheme)
+            cols = [int(np.flatnonzero(np.all(idx == np.array(q), axis=1))[0]) for q in stencil]
+            offs = [tuple(int(round((src_pos[c][i] - src_pos[home][i]) / unit)) for i in range(3)) for c in cols]
+            tgt = tuple(Fraction(int(round(X[i] - src_pos[home][i])), int(unit)) for i in range(3))
+            exact = chk.exact_pinned_fit(offs, cols.index(home), tgt, scheme)
+            want = np.zeros(W.shape[1])
+            for c, v in zip(cols, exact):
+                want[c] += float(v)
+            assert np.abs(W[r] - want).max() < 1e-14 * np.abs(want).sum()
