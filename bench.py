@@ -81,7 +81,7 @@ def algorithmic_bytes(op, orientation, subface, U, elem_bytes):
     return int(sum(per[(o, s)] * counts[o, s] for o in range(6) for s in range(9)))
 
 
-KERNEL_SOURCES = ("ft_device.h", "ft_kernels.hip", "ft_mfma.hip")
+KERNEL_SOURCES = ("ft_device.h", "ft_kernels.hip", "ft_mfma.hip", "ft_kernels.h")
 
 
 def recorded_traffic(kernel_name, mode="f64"):

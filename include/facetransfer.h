@@ -24,7 +24,13 @@
  * A hanging (fine) face is one of the 3x3 subfaces of its coarse face
  * (three-partitioning, Section 2); subface s = sb + 3*sc with sb, sc in 0..2
  * covers coarse columns [sb*p/3, (sb+1)*p/3) x [sc*p/3, (sc+1)*p/3) of the
- * coarse face.  Coarse and fine face buffers have the same shape.
+ * coarse face.  Coarse and fine face buffers have the same shape.  When p is
+ * not a multiple of 3 (Section 5.3 times such sizes) a coarse column may
+ * straddle two fine faces: interpolation writes the fine face's own cells,
+ * and restriction writes the coarse columns whose centres lie on the fine
+ * face (every coarse centre lies on exactly one fine face, on one of its
+ * fine centres); the averaging restriction of a straddling column takes
+ * that fine column instead of the mean of three.
  *
  * Interpolation (Q^f = P Q^c, Section 2) reads both halves of the coarse
  * face buffer and writes the fine face buffer's coarse-side half (its halo).
@@ -42,7 +48,7 @@
  * degree 3), shifted toward the face interior at face edges.  Coinciding
  * centres are copied bit for bit.
  *
- * Supported sizes: p a multiple of 3 with 6 <= p <= 48; k in {2, 3} for every
+ * Supported sizes: 6 <= p <= 48; k in {2, 3} for every
  * scheme and k = 1 (the finite-volume halo of Section 2) for FT_DLINEAR; there
  * the single fine ghost layer is interpolated between coarse layer 0 and the
  * coarse face's fine-side layer, and the coarse halo layer is extrapolated

@@ -21,6 +21,10 @@ Conventions (the two-dimensional counterparts of the geometry module):
 * Stencils (Appendix C reading of the fit module): the 3 x 3 box around the
   expansion cell with its centre clamped into [1, e - 2] per axis, plus, for
   degree 3, the points two cells away along each axis where inside the data.
+* p need not be a multiple of 3: as in three dimensions, a fine face
+  restricts into the coarse columns whose centres it holds, and the
+  averaging restriction of a coarse column that straddles two fine faces
+  takes the fine column through its centre.
 """
 
 from fractions import Fraction
@@ -92,8 +96,8 @@ def fine_ghost_half(o, k, idx):
 def _check(scheme, p, k, o, s):
     if scheme not in (DLINEAR, TAYLOR2, TAYLOR3):
         raise ValueError(f"unknown scheme {scheme}")
-    if p < 6 or p % 3:
-        raise ValueError(f"p must be a multiple of 3 and >= 6, got {p}")
+    if p < 6:
+        raise ValueError(f"p must be >= 6, got {p}")
     if k not in (1, 2, 3) or (k == 1 and scheme != DLINEAR):
         raise ValueError("k must be 2 or 3 (or 1 for the d-linear scheme)")
     if not (0 <= o < 4 and 0 <= s < 3):
@@ -152,8 +156,13 @@ def _dlinear_restriction_row(o, p, k, target_pos, fine_pos, ext):
     side = 1.0 if fine_on_plus_side(o) else -1.0
     depth_T = side * target_pos[a]
     lo = target_pos[b] - 1.5
-    tang = [i for i in range(ext[b]) if lo < fine_pos[b][i] < lo + 3.0]
-    assert len(tang) == 3
+    under = [i for i in range(ext[b]) if lo < fine_pos[b][i] < lo + 3.0]
+    if len(under) == 3:
+        tang = {i: 1.0 / 3.0 for i in under}
+    else:
+        # p not a multiple of 3: the fine column through the coarse centre
+        tang = {i: 1.0 for i in under if fine_pos[b][i] == target_pos[b]}
+        assert len(tang) == 1
     layers = sorted(range(ext[a]), key=lambda i: side * fine_pos[a][i])
     inner = [i for i in layers if side * fine_pos[a][i] > 0]
     covered = [i for i in inner if abs(side * fine_pos[a][i] - depth_T) < 1.5]
@@ -166,10 +175,10 @@ def _dlinear_restriction_row(o, p, k, target_pos, fine_pos, ext):
         normal = {i1: 1.0 - t, i2: t}
     row = np.zeros(cell_count(p, k))
     for ia, wa in normal.items():
-        for ib in tang:
+        for ib, wb in tang.items():
             idx = [0, 0]
             idx[a], idx[b] = ia, ib
-            row[cell_index(ext, idx)] += wa / 3.0
+            row[cell_index(ext, idx)] += wa * wb
     return row
 
 
@@ -190,9 +199,9 @@ def restriction_operator(scheme, p, k, o, s):
     for tc in cells:
         if not coarse_fine_side_half(o, k, tc):
             continue
-        if not (s * (p // 3) <= tc[b] < (s + 1) * (p // 3)):
-            continue
         XT = coarse_position(o, p, k, tc)
+        if not (s * p <= XT[b] < (s + 1) * p):  # coarse centres on this fine face
+            continue
         if scheme == DLINEAR:
             row = _dlinear_restriction_row(o, p, k, XT, per_axis_pos, ext)
         else:

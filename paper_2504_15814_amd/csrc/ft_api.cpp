@@ -212,6 +212,67 @@ int check_copy(int p, int k, int64_t n, const void* sel, const void* off_a, cons
   return FT_OK;
 }
 
+// COO entries of the 1/9 (2D: 1/3) segment of `op` for one (orientation,
+// subface), in the face buffer's physical cell numbering.
+void segment_entries(const ft_operator* op, int orientation, int subface,
+                     std::vector<int64_t>& rr, std::vector<int64_t>& cc, std::vector<double>& vv) {
+  const bool d3 = op->dim == 3;
+  const int p = op->p, k = op->k, E = op->E, R = op->R;
+  const ft::FaceView st = d3 ? ft::buffer_view(orientation % 3, p, k)
+                             : ft::buffer_view2d(orientation % 2, p, k);
+  int nbase, nsign;
+  ft::normal_map_side(op->direction, orientation < (d3 ? 3 : 2), k, &nbase, &nsign);
+  const int sb = d3 ? subface % 3 : subface, sc = d3 ? subface / 3 : 0;
+  for (int ec = 0; ec < (d3 ? E : 1); ++ec)
+    for (int eb = 0; eb < E; ++eb) {
+      // anchor columns in the source face (ab, ac) and the first destination
+      // columns (db0, dc0); see the anchor helpers in ft_internal.h
+      int ab, ac = 0, db0, dc0 = 0;
+      if (op->direction == 0) {
+        ab = ft::interp_anchor0(sb, p) + eb;
+        if (!ft::interp_anchor_valid(ab, sb, p)) continue;
+        db0 = 3 * ab - sb * p;
+        if (d3) {
+          ac = ft::interp_anchor0(sc, p) + ec;
+          if (!ft::interp_anchor_valid(ac, sc, p)) continue;
+          dc0 = 3 * ac - sc * p;
+        }
+      } else {
+        db0 = ft::restrict_anchor0(sb, p) + eb;
+        if (!ft::restrict_anchor_valid(db0, sb, p)) continue;
+        ab = 3 * db0 + 1 - sb * p;
+        if (d3) {
+          dc0 = ft::restrict_anchor0(sc, p) + ec;
+          if (!ft::restrict_anchor_valid(dc0, sc, p)) continue;
+          ac = 3 * dc0 + 1 - sc * p;
+        }
+      }
+      const auto& blk = op->blocks[ft::axis_class(ab, p) * ft::kAxisClasses +
+                                   (d3 ? ft::axis_class(ac, p) : 0)];
+      const int anchor = ab * st.sb + ac * st.sc;
+      for (int r = 0; r < R; ++r) {
+        int dcell;
+        if (op->direction == 0) {
+          const int g = d3 ? r / 9 : r / 3, tb = d3 ? (r / 3) % 3 : r % 3, tc = d3 ? r % 3 : 0;
+          const int jb = db0 + tb, jc = dc0 + tc;
+          if (jb < 0 || jb >= p || (d3 && (jc < 0 || jc >= p))) continue;  // other fine face
+          dcell = (nbase + nsign * g) * st.sa + jb * st.sb + jc * st.sc;
+        } else {
+          dcell = (nbase + nsign * r) * st.sa + db0 * st.sb + dc0 * st.sc;
+        }
+        for (int q = 0; q < blk.width; ++q) {
+          const double w = blk.weights[(size_t)q * R + r];
+          if (w == 0.0) continue;
+          int n, db, dc;
+          ft::unpack_point(blk.points[q], &n, &db, &dc);
+          rr.push_back(dcell);
+          cc.push_back(anchor + (nbase + nsign * n) * st.sa + db * st.sb + dc * st.sc);
+          vv.push_back(w);
+        }
+      }
+    }
+}
+
 }  // namespace
 
 void ft::set_last_error(const std::string& msg) { g_last_error = msg; }
@@ -226,8 +287,7 @@ int build_transfer_operator(int direction, int scheme, int p, int k, int flags,
     return fail(FT_ERR_INVALID, "direction must be FT_INTERPOLATE or FT_RESTRICT");
   if (scheme != FT_DLINEAR && scheme != FT_TAYLOR2 && scheme != FT_TAYLOR3)
     return fail(FT_ERR_INVALID, "scheme must be FT_DLINEAR, FT_TAYLOR2 or FT_TAYLOR3");
-  if (p < 6 || p > ft::kMaxP || p % 3 != 0)
-    return fail(FT_ERR_UNSUPPORTED, "p must be a multiple of 3 in [6, 48]");
+  if (p < 6 || p > ft::kMaxP) return fail(FT_ERR_UNSUPPORTED, "p must be in [6, 48]");
   if (k < 1 || k > 3) return fail(FT_ERR_UNSUPPORTED, "k must be 1, 2 or 3");
   if (k == 1 && scheme != FT_DLINEAR)
     return fail(FT_ERR_UNSUPPORTED, "k = 1 is supported by FT_DLINEAR only");
@@ -395,20 +455,15 @@ int transfer_operator_info(const ft_operator* op, int64_t* info, int n_info) {
     widest = std::max<int64_t>(widest, op->blocks[c].width);
     wbytes += (int64_t)op->blocks[c].weights.size() * 8;
   }
-  int64_t nnz = 0;
   const bool d3 = op->dim == 3;
+  int64_t nnz = 0;
   {
     // Nonzero weights of the middle segment (orientation 0, subface 4; in 2D
     // subface 1).
-    const int E = op->E;
-    for (int ec = 0; ec < (d3 ? E : 1); ++ec)
-      for (int eb = 0; eb < E; ++eb) {
-        const int ab = op->direction == 0 ? E + eb : 3 * eb + 1;
-        const int ac = op->direction == 0 ? E + ec : 3 * ec + 1;
-        const int cls = ft::axis_class(ab, op->p) * ft::kAxisClasses +
-                        (d3 ? ft::axis_class(ac, op->p) : 0);
-        for (double w : op->blocks[cls].weights) nnz += (w != 0.0);
-      }
+    std::vector<int64_t> rr, cc;
+    std::vector<double> vv;
+    segment_entries(op, 0, d3 ? 4 : 1, rr, cc, vv);
+    nnz = (int64_t)vv.size();
   }
   const int64_t vals[11] = {op->direction, op->scheme, op->p, op->k, op->R,
                             d3 ? (int64_t)op->E * op->E : (int64_t)op->E, blocks, widest, nnz,
@@ -426,40 +481,9 @@ int transfer_operator_segment(const ft_operator* op, int orientation, int subfac
   if (orientation < 0 || orientation > (d3 ? 5 : 3) || subface < 0 || subface > (d3 ? 8 : 2))
     return fail(FT_ERR_INVALID, d3 ? "orientation must be 0..5 and subface 0..8"
                                    : "orientation must be 0..3 and subface 0..2 (2D)");
-  const int p = op->p, k = op->k, E = op->E, R = op->R;
-  const ft::FaceView st = d3 ? ft::buffer_view(orientation % 3, p, k)
-                             : ft::buffer_view2d(orientation % 2, p, k);
-  int nbase, nsign;
-  ft::normal_map_side(op->direction, orientation < (d3 ? 3 : 2), k, &nbase, &nsign);
-  const int sb = d3 ? subface % 3 : subface, sc = d3 ? subface / 3 : 0;
   std::vector<int64_t> rr, cc;
   std::vector<double> vv;
-  for (int ec = 0; ec < (d3 ? E : 1); ++ec)
-    for (int eb = 0; eb < E; ++eb) {
-      const int ab = op->direction == 0 ? sb * E + eb : 3 * eb + 1;
-      const int ac = d3 ? (op->direction == 0 ? sc * E + ec : 3 * ec + 1) : 0;
-      const auto& blk = op->blocks[ft::axis_class(ab, p) * ft::kAxisClasses +
-                                   (d3 ? ft::axis_class(ac, p) : 0)];
-      const int anchor = ab * st.sb + ac * st.sc;
-      for (int r = 0; r < R; ++r) {
-        int dcell;
-        if (op->direction == 0) {
-          const int g = d3 ? r / 9 : r / 3, tb = d3 ? (r / 3) % 3 : r % 3, tc = d3 ? r % 3 : 0;
-          dcell = (nbase + nsign * g) * st.sa + (3 * eb + tb) * st.sb + (3 * ec + tc) * st.sc;
-        } else {
-          dcell = (nbase + nsign * r) * st.sa + (sb * E + eb) * st.sb + (sc * E + ec) * st.sc;
-        }
-        for (int q = 0; q < blk.width; ++q) {
-          const double w = blk.weights[(size_t)q * R + r];
-          if (w == 0.0) continue;
-          int n, db, dc;
-          ft::unpack_point(blk.points[q], &n, &db, &dc);
-          rr.push_back(dcell);
-          cc.push_back(anchor + (nbase + nsign * n) * st.sa + db * st.sb + dc * st.sc);
-          vv.push_back(w);
-        }
-      }
-    }
+  segment_entries(op, orientation, subface, rr, cc, vv);
   *n_entries = (int64_t)rr.size();
   if (capacity < (int64_t)rr.size()) return fail(FT_ERR_INVALID, "capacity too small");
   if (!rows || !cols || !vals) return fail(FT_ERR_INVALID, "NULL output array");

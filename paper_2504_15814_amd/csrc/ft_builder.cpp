@@ -238,8 +238,23 @@ bool block_rows(const ft_operator* op, int ab, int ac, std::vector<Row>* rows, s
   // Restriction: coarse target layer l (centre 3l + 3/2 fine widths into the
   // fine side); its nearest fine cell is layer min(3l+1, k-1) of the
   // coincident column (ab, ac) = (3 mu + 1) along b (and c).
-  const int rc = dim == 3 ? 1 : 0;
-  const long double ncols = dim == 3 ? 9.0L : 3.0L;
+  // Averaging along a tangential axis: the three fine columns under the
+  // coarse column when all belong to this fine face, else (p not a multiple
+  // of 3, the coarse column straddles two fine faces) the one through its
+  // centre.
+  auto tangential = [&](int j, bool axis_exists) {
+    std::map<int, long double> w;
+    if (!axis_exists) {
+      w[0] = 1.0L;
+    } else if (j >= 1 && j + 1 <= p - 1) {
+      for (int d = -1; d <= 1; ++d) w[d] = 1.0L / 3.0L;
+    } else {
+      w[0] = 1.0L;
+    }
+    return w;
+  };
+  const auto wtb = tangential(ab, true);
+  const auto wtc = tangential(ac, dim == 3);
   for (int l = 0; l < k; ++l) {
     const int eta = std::min(3 * l + 1, k - 1);
     if (op->scheme == FT_DLINEAR) {
@@ -253,8 +268,8 @@ bool block_rows(const ft_operator* op, int ab, int ac, std::vector<Row>* rows, s
       }
       Row r;
       for (auto& [i0, w0] : wn)
-        for (int db = -1; db <= 1; ++db)
-          for (int dc = -rc; dc <= rc; ++dc) r[Cell(i0, ab + db, ac + dc)] += w0 / ncols;
+        for (auto& [db, w1] : wtb)
+          for (auto& [dc, w2] : wtc) r[Cell(i0, ab + db, ac + dc)] += w0 * w1 * w2;
       rows->push_back(r);
     } else {
       std::vector<Row> one;
@@ -270,7 +285,7 @@ bool block_rows(const ft_operator* op, int ab, int ac, std::vector<Row>* rows, s
 
 std::string build_tables(ft_operator* op) {
   const int p = op->p, k = op->k, dim = op->dim;
-  op->E = p / 3;
+  op->E = anchors_per_axis(op->direction, p);
   op->R = op->direction == 0 ? (dim == 3 ? 9 : 3) * k : k;
   op->copy_row = -1;
   op->copy_n = 0;
@@ -286,11 +301,23 @@ std::string build_tables(ft_operator* op) {
   // Representative anchor column of each axis class.
   int rep[kAxisClasses];
   for (int i = 0; i < kAxisClasses; ++i) rep[i] = -1;
-  for (int e = 0; e < (op->direction == 0 ? p : p / 3); ++e) {
-    const int m = op->direction == 0 ? e : 3 * e + 1;
-    const int c = axis_class(m, p);
-    if (rep[c] < 0) rep[c] = m;
-  }
+  // Anchor columns that occur: every coarse column (interpolation), or every
+  // fine column that coincides with a coarse centre on some subface
+  // (restriction; 3m + 1 for multiples of 3, any column otherwise).
+  for (int sd = 0; sd < 3; ++sd)
+    for (int e = 0; e < op->E; ++e) {
+      int m;
+      if (op->direction == 0) {
+        m = interp_anchor0(sd, p) + e;
+        if (!interp_anchor_valid(m, sd, p)) continue;
+      } else {
+        const int mc = restrict_anchor0(sd, p) + e;
+        if (!restrict_anchor_valid(mc, sd, p)) continue;
+        m = 3 * mc + 1 - sd * p;
+      }
+      const int c = axis_class(m, p);
+      if (rep[c] < 0) rep[c] = m;
+    }
   // Two dimensions: one class per anchor along b, stored at slot cb * 5.
   for (int cb = 0; cb < kAxisClasses; ++cb)
     for (int cc = 0; cc < kAxisClasses; ++cc) {

@@ -93,17 +93,37 @@ __device__ __forceinline__ void apply_item(
   normal_map_side(DIR, o < (DIM == 3 ? 3 : 2), k, &nbase, &nsign);
   const int sb = DIM == 3 ? s % 3 : s, sc = DIM == 3 ? s / 3 : 0;
 
-  // Anchor column in the source face and the block that serves it.
-  const int anc_b = DIR == 0 ? sb * E + eb : 3 * eb + 1;
-  const int anc_c = DIM == 3 ? (DIR == 0 ? sc * E + ec : 3 * ec + 1) : 0;
+  // Anchor columns in the source face (anc) and first destination columns
+  // (dst: the fine column of row tb = 0, or the coarse target column).  With
+  // p not a multiple of 3 some anchors of the E x E grid hold no fine column
+  // of this subface (nothing to do) and some interpolation rows belong to the
+  // neighbouring fine face (not stored).
+  int anc_b, anc_c = 0, dst_b, dst_c = 0;
+  if (DIR == 0) {
+    anc_b = interp_anchor0(sb, p) + eb;
+    dst_b = 3 * anc_b - sb * p;
+    if (DIM == 3) {
+      anc_c = interp_anchor0(sc, p) + ec;
+      dst_c = 3 * anc_c - sc * p;
+    }
+    if (!interp_anchor_valid(anc_b, sb, p) || (DIM == 3 && !interp_anchor_valid(anc_c, sc, p)))
+      return;
+  } else {
+    dst_b = restrict_anchor0(sb, p) + eb;
+    anc_b = 3 * dst_b + 1 - sb * p;
+    if (DIM == 3) {
+      dst_c = restrict_anchor0(sc, p) + ec;
+      anc_c = 3 * dst_c + 1 - sc * p;
+    }
+    if (!restrict_anchor_valid(dst_b, sb, p) || (DIM == 3 && !restrict_anchor_valid(dst_c, sc, p)))
+      return;
+  }
   const int cls = axis_class(anc_b, p) * kAxisClasses + (DIM == 3 ? axis_class(anc_c, p) : 0);
   const int width = op->width[cls];
   const int start = op->start[cls];
   const int anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
   const int nstride = nsign * sv.sa;
   // First destination cell of this anchor and the strides of its rows.
-  const int dst_b = DIR == 0 ? 3 * eb : sb * E + eb;
-  const int dst_c = DIM == 3 ? (DIR == 0 ? 3 * ec : sc * E + ec) : 0;
   const int dst_cell0 = dv.base + nbase * dv.sa + dst_b * dv.sb + dst_c * dv.sc;
   const int dstride = nsign * dv.sa;
 
@@ -157,6 +177,9 @@ __device__ __forceinline__ void apply_item(
       if (DIR == 0) {
         const int g = DIM == 3 ? r / 9 : r / 3, tb = DIM == 3 ? (r / 3) % 3 : r % 3;
         const int tc = DIM == 3 ? r % 3 : 0;
+        if ((unsigned)(dst_b + tb) >= (unsigned)p ||
+            (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p))
+          continue;  // a fine cell of the neighbouring fine face
         dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
       } else {
         dcell = dst_cell0 + r * dstride;
@@ -217,13 +240,20 @@ __device__ __forceinline__ void mfma_item(
   const int nstride = nsign * sv.sa;
   const int dstride = nsign * dv.sa;
   const int sb = DIM == 3 ? s % 3 : s, sc = DIM == 3 ? s / 3 : 0;
-  const int anc_b = sb * E + eb, anc_c = DIM == 3 ? sc * E + ec : 0;
+  // Anchor coarse columns and the fine columns of their rows tb = 0 (see
+  // apply_item: with p not a multiple of 3 some anchors are empty and some
+  // rows belong to the neighbouring fine face).
+  const int anc_b = interp_anchor0(sb, p) + eb;
+  const int anc_c = DIM == 3 ? interp_anchor0(sc, p) + ec : 0;
+  if (!interp_anchor_valid(anc_b, sb, p) || (DIM == 3 && !interp_anchor_valid(anc_c, sc, p)))
+    return;
+  const int dst_b = 3 * anc_b - sb * p, dst_c = DIM == 3 ? 3 * anc_c - sc * p : 0;
   const int cls = axis_class(anc_b, p) * kAxisClasses + (DIM == 3 ? axis_class(anc_c, p) : 0);
   const int width = op->width[cls];
   const int start = op->start[cls];
   const int nsteps = (width + kMfmaK - 1) / kMfmaK;
   const int anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
-  const int dst_cell0 = dv.base + nbase * dv.sa + 3 * eb * dv.sb + 3 * ec * dv.sc;
+  const int dst_cell0 = dv.base + nbase * dv.sa + dst_b * dv.sb + dst_c * dv.sc;
 
   const FT_CONST bf16x8* wt = cptr(reinterpret_cast<const bf16x8*>(op->wbf16));
   const FT_CONST int* pts = cptr(op->stencil) + start;
@@ -324,6 +354,9 @@ __device__ __forceinline__ void mfma_item(
       for (int m = 0; m < R; ++m) {
         const int g = DIM == 3 ? m / 9 : m / 3, tb = DIM == 3 ? (m / 3) % 3 : m % 3;
         const int tc = DIM == 3 ? m % 3 : 0;
+        if ((unsigned)(dst_b + tb) >= (unsigned)p ||
+            (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p))
+          continue;  // a fine cell of the neighbouring fine face
         const int dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
         __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
       }

@@ -35,6 +35,32 @@ __host__ __device__ inline int axis_class(int m, int p) {
   return lo < 2 ? lo : 4 - hi;
 }
 
+// Anchors along one tangential axis of fine subface digit sd (0..2); p need
+// not be a multiple of 3.  Fine column j of the subface is global fine column
+// J = sd*p + j, inside coarse column J / 3 at offset (J % 3 - 1) / 3.
+// Interpolation: the anchors are the coarse columns m = interp_anchor0 + e
+// that hold at least one fine column of the subface.
+__host__ __device__ inline int interp_anchor0(int sd, int p) { return (sd * p) / 3; }
+__host__ __device__ inline bool interp_anchor_valid(int m, int sd, int p) {
+  return 3 * m <= sd * p + p - 1;
+}
+// Restriction: the coarse columns m = restrict_anchor0 + e whose centre lies
+// on the subface; it coincides with the subface's fine column 3m + 1 - sd*p.
+__host__ __device__ inline int restrict_anchor0(int sd, int p) { return (sd * p + 1) / 3; }
+__host__ __device__ inline bool restrict_anchor_valid(int m, int sd, int p) {
+  return 3 * m + 1 - sd * p <= p - 1;
+}
+// Largest number of anchors per axis over the three subface digits.
+__host__ __device__ inline int anchors_per_axis(int direction, int p) {
+  int best = 0;
+  for (int sd = 0; sd < 3; ++sd) {
+    const int n = direction == 0 ? (sd * p + p - 1) / 3 - interp_anchor0(sd, p) + 1
+                                 : (sd * p + p - 2) / 3 - restrict_anchor0(sd, p) + 1;
+    best = n > best ? n : best;
+  }
+  return best;
+}
+
 // Physical strides (in cells) of the normal and tangential axes of a face
 // buffer with normal axis a: cell = i0 + e0 * (i1 + e1 * i2).
 struct FaceStrides {
@@ -134,7 +160,7 @@ struct DevOp {
   int direction, scheme, p, k;
   int dim;        // 3, or 2 for two-dimensional faces
   int R;          // rows per expansion cell
-  int E;          // expansion cells per axis and subface (p / 3)
+  int E;          // anchors per axis and subface (p / 3 when 3 divides p)
   int copy_row;   // row that is an exact copy of a source cell, or -1
   int copy_n;     // normal coordinate of that source cell (tangential = anchor)
   int width[kClasses];  // stencil width per block (0 = class unused)

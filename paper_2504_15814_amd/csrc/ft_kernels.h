@@ -27,7 +27,10 @@ struct LaunchArgs {
 // order, so every shape gives bitwise identical results).
 struct LaunchConfig {
   int waves_per_block = 4;  // 1..4
-  int xcd_remap = 0;
+  // Consecutive blocks on one XCD, so that the anchors of a face share one
+  // L2: halves the interpolation's L2 misses (Taylor-3: 1.49 -> 0.75 GB per
+  // 20,000 faces) and gives restriction ~2 %.
+  int xcd_remap = 1;
 };
 
 hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const LaunchConfig& cfg,

@@ -326,15 +326,17 @@ class MixedBatch:
 
 
 def workload4(n_faces=50000, device="cpu", dtype=torch.float32, U=59, seed=SEED_BASE + 4,
-              k_values=(2, 3)):
+              k_values=(2, 3), p_values=(6, 9, 12)):
     """50,000 faces: p in {6, 9, 12} at 30/50/20 %, k in {2, 3} uniform, scheme
     in {d-linear, Taylor-2, Taylor-3} uniform, direction Bernoulli(1/2)
     interleaved; bump fields with 1e-3 noise, U = 59.  Other halo depths can
     be mixed in with k_values (uniform over them); faces drawn with k = 1
-    use the d-linear scheme, the only one defined there."""
+    use the d-linear scheme, the only one defined there.  p_values replaces
+    the three patch sizes (same 30/50/20 % split)."""
     gen = torch.Generator().manual_seed(seed)
     r = torch.rand(n_faces, generator=gen)
-    p = torch.where(r < 0.3, 6, torch.where(r < 0.8, 9, 12)).to(torch.int64)
+    p0, p1, p2 = p_values
+    p = torch.where(r < 0.3, p0, torch.where(r < 0.8, p1, p2)).to(torch.int64)
     if tuple(k_values) == (2, 3):
         k = torch.randint(2, 4, (n_faces,), generator=gen)
     else:
@@ -355,7 +357,7 @@ def workload4(n_faces=50000, device="cpu", dtype=torch.float32, U=59, seed=SEED_
                     torch.zeros(total, dtype=dtype, device=device), torch.zeros(total, dtype=dtype, device=device))
     noise_seed = int(torch.randint(0, 2**62, (1,), generator=gen).item())
     noise_gen = torch.Generator(device=device).manual_seed(noise_seed)
-    for pp in (6, 9, 12):
+    for pp in p_values:
         for kk in k_values:
             sel = torch.nonzero((p == pp) & (k == kk)).flatten()
             if sel.numel() == 0:

@@ -45,7 +45,6 @@ def test_version_and_empty_error():
     [
         ((2, 2, 9, 3), api.FT_ERR_INVALID),   # bad direction
         ((0, 4, 9, 3), api.FT_ERR_INVALID),   # bad scheme
-        ((0, 2, 10, 3), api.FT_ERR_UNSUPPORTED),  # p not a multiple of 3
         ((0, 2, 3, 3), api.FT_ERR_UNSUPPORTED),   # p too small
         ((0, 2, 51, 3), api.FT_ERR_UNSUPPORTED),  # p too large
         ((0, 2, 9, 1), api.FT_ERR_UNSUPPORTED),   # k = 1
@@ -271,3 +270,30 @@ def test_2d_info_and_ranges():
     assert lib.transfer_operator_segment(op.handle, 0, 3, 0, None, None, None, ctypes.byref(n)) == api.FT_ERR_INVALID
     h = ctypes.c_void_p()
     assert lib.build_transfer_operator(0, 2, 9, 1, api.FT_BUILD_HOST_ONLY | api.FT_BUILD_2D, ctypes.byref(h)) == api.FT_ERR_UNSUPPORTED
+
+
+# Patch sizes that are not multiples of 3.
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+@pytest.mark.parametrize("p,k", [(7, 2), (8, 3), (10, 2), (11, 3)])
+def test_library_segments_equal_oracle_general_p(direction, scheme, p, k):
+    test_library_segments_equal_oracle(direction, scheme, p, k)
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("p", [7, 8, 10])
+def test_library_segments_equal_oracle_general_p_k1_and_2d(direction, p):
+    test_library_segments_equal_oracle(direction, 1, p, 1)
+    for scheme, k in ((1, 1), (2, 2), (3, 3)):
+        test_library_2d_segments_equal_oracle(direction, scheme, p, k)
+
+
+def test_general_p_anchor_counts():
+    """Anchors per axis: p / 3 for multiples of 3; otherwise the largest
+    number of coarse columns a subface touches (interpolation) or holds the
+    centres of (restriction)."""
+    for p, ei, er in ((6, 2, 2), (9, 3, 3), (7, 3, 3), (8, 4, 3), (10, 4, 4), (11, 5, 4)):
+        assert api.build_transfer_operator(0, 2, p, 2, api.FT_BUILD_HOST_ONLY).info()["anchors"] == ei * ei
+        assert api.build_transfer_operator(1, 2, p, 2, api.FT_BUILD_HOST_ONLY).info()["anchors"] == er * er

@@ -53,7 +53,8 @@ def oracle_out(direction, scheme, b, src, before, absolute=False):
     return out, mask, copy
 
 
-CASES = [(s, p, k) for s in (1, 2, 3) for p, k in ((6, 2), (9, 3), (12, 3))] + [(1, 9, 1), (1, 12, 1)]
+CASES = [(s, p, k) for s in (1, 2, 3) for p, k in ((6, 2), (9, 3), (12, 3), (8, 3), (10, 2))] + \
+    [(1, 9, 1), (1, 12, 1), (1, 7, 1)]
 
 
 @pytest.mark.parametrize("scheme,p,k", CASES)
@@ -71,7 +72,7 @@ def test_2d_parity_f64(scheme, p, k, U):
 
 
 @pytest.mark.parametrize("mode", [api.FT_F32, api.FT_F32_BF16X3, api.FT_F32_BF16X6])
-@pytest.mark.parametrize("scheme,p,k", [(1, 9, 3), (2, 9, 3), (3, 9, 3), (3, 6, 2), (1, 9, 1)])
+@pytest.mark.parametrize("scheme,p,k", [(1, 9, 3), (2, 9, 3), (3, 9, 3), (3, 6, 2), (1, 9, 1), (3, 8, 3)])
 def test_2d_float32_modes(mode, scheme, p, k):
     dev = require_gpu()
     U = 59

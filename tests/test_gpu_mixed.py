@@ -78,6 +78,16 @@ def test_halo_depth_one_modes(dev, mode, U):
     check_mode(batch, 1, mode)
 
 
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("p,k", [(8, 3), (10, 2)])
+def test_matrix_core_path_general_p(dev, mode, p, k):
+    """p not a multiple of 3: partial anchors and skipped rows on the matrix
+    cores too."""
+    batch = wl.uniform_faces(20, p, k, 59, seed=97 + p + k + mode, device=dev)
+    for scheme in (1, 3):
+        check_mode(batch, scheme, mode)
+
+
 def test_restriction_modes_share_the_float32_path(b59):
     outs = []
     for mode in MODES:

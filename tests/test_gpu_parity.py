@@ -77,6 +77,21 @@ def test_halo_depth_one_dlinear(dev, p, U):
         gh.check_parity(direction, 1, batch, dtype=torch.float32, tol=1e-5)
 
 
+@pytest.mark.parametrize("p,k", [(7, 2), (8, 3), (10, 3), (11, 2)])
+def test_patch_sizes_not_multiples_of_three(dev, p, k):
+    """Fine and coarse cells do not align at the subface boundaries: partial
+    anchors, rows of the neighbouring fine face skipped, restriction columns
+    chosen by their centres."""
+    batch = wl.uniform_faces(40, p, k, 59, seed=3000 + 10 * p + k, device=dev)
+    for direction in DIRS:
+        for scheme in SCHEMES:
+            gh.check_parity(direction, scheme, batch)
+        gh.check_parity(direction, 3, batch, dtype=torch.float32, tol=1e-5)
+    k1 = wl.uniform_faces(20, p, 1, 7, seed=3100 + p, device=dev)
+    for direction in DIRS:
+        gh.check_parity(direction, 1, k1)
+
+
 def test_empty_batch_is_a_noop(dev):
     batch = wl.uniform_faces(3, 9, 3, 5, seed=3, device=dev)
     for direction in DIRS:

@@ -169,7 +169,7 @@ def unfused_restrict(op, b, fine, coarse, faces_per_coarse):
     api.scatter_patch_faces(p, k, gface, gpatch, gbuf, OUTER, U, cbuf, coarse)
 
 
-SHAPES = [(6, 2, 7), (9, 3, 59), (12, 3, 70)]
+SHAPES = [(6, 2, 7), (9, 3, 59), (12, 3, 70), (8, 3, 13)]
 
 
 @pytest.mark.parametrize("scheme", [oracle.DLINEAR, oracle.TAYLOR2, oracle.TAYLOR3])

@@ -202,3 +202,33 @@ def test_plan_with_halo_depth_one(dev):
             assert torch.equal(pc, rc) and torch.equal(pf, rf)
         for op in ops.values():
             assert op.errors() == 0
+
+
+def test_plan_with_patch_sizes_not_multiples_of_three(dev):
+    """A mix of p = 7, 8, 10 (partial anchors in every segment): the plan
+    equals the per-batch calls bit for bit, and they equal the oracle on a
+    sample (float64)."""
+    mb = wl.workload4(n_faces=600, device=dev, dtype=torch.float64, seed=321, p_values=(7, 8, 10))
+    ops = build_ops(mb)
+    rc, rf = per_batch_reference(mb, ops, None)
+    _, pc, pf = run_plan(mb, ops, None)
+    assert torch.equal(pc, rc) and torch.equal(pf, rf)
+    for op in ops.values():
+        assert op.errors() == 0
+    coarse_in, fine_in = mb.coarse.cpu().numpy(), mb.fine.cpu().numpy()
+    pc_np, pf_np = pc.cpu().numpy(), pf.cpu().numpy()
+    co, fo = mb.coarse_offset.cpu().numpy(), mb.fine_offset.cpu().numpy()
+    orient, sub = mb.orientation.cpu().numpy(), mb.subface.cpu().numpy()
+    U = mb.U
+    for (d, sch, p, k), idx in mb.groups().items():
+        for f in idx[:2].tolist():
+            rows, W = oracle.transfer_operator(d, sch, p, k, int(orient[f]), int(sub[f]))
+            ncell = 2 * k * p * p
+            if d == 0:
+                x = coarse_in[co[f]:co[f] + ncell * U].reshape(ncell, U)
+                got = pf_np[fo[f]:fo[f] + ncell * U].reshape(ncell, U)[rows]
+            else:
+                x = fine_in[fo[f]:fo[f] + ncell * U].reshape(ncell, U)
+                got = pc_np[co[f]:co[f] + ncell * U].reshape(ncell, U)[rows]
+            want = W @ x
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()

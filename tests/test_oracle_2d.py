@@ -302,3 +302,22 @@ def test_swapped_normal_side_is_caught(monkeypatch):
     monkeypatch.setattr(o2, "fine_on_plus_side", lambda o: int(o) >= 2)
     assert _fails(test_rows_sum_to_one_and_segments_tile, 0, 1)
     assert _fails(test_rows_sum_to_one_and_segments_tile, 1, 2)
+
+
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_general_p_2d(scheme, direction):
+    """p not a multiple of 3: reproduction, row sums, and restriction columns
+    that tile the coarse halo (the same reading as in 3D)."""
+    rng = np.random.default_rng(40 + scheme + direction)
+    for p, k in ((7, 2), (8, 3), (10, 2)):
+        worst = max(reproduction_error(scheme, p, k, o, s, rng, direction) for o in range(4) for s in range(3))
+        assert worst < 1e-12
+        for o in range(4):
+            seen = []
+            for s in range(3):
+                rows, W = o2.transfer_operator(direction, scheme, p, k, o, s)
+                assert np.allclose(W.sum(axis=1), 1.0, atol=1e-13)
+                seen.extend(rows.tolist())
+            if direction == 1:
+                assert len(seen) == len(set(seen)) == k * p
