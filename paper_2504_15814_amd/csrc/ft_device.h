@@ -26,6 +26,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ft_internal.h"
 
 namespace ft {
@@ -171,24 +173,35 @@ __device__ __forceinline__ void apply_item(
         if (r != COPY) acc[r] = fma(A(w[r]), x, acc[r]);
     }
     if (!act) continue;
+    // Interpolation anchors whose fine cells all belong to this fine face
+    // (every anchor when 3 divides p) store straight through; the others skip
+    // the cells of the neighbouring fine face.
+    const bool full =
+        DIR == 1 || (dst_b >= 0 && dst_b + 2 < p && (DIM == 2 || (dst_c >= 0 && dst_c + 2 < p)));
+    auto store_rows = [&](auto check) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      int dcell;
-      if (DIR == 0) {
-        const int g = DIM == 3 ? r / 9 : r / 3, tb = DIM == 3 ? (r / 3) % 3 : r % 3;
-        const int tc = DIM == 3 ? r % 3 : 0;
-        if ((unsigned)(dst_b + tb) >= (unsigned)p ||
-            (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p))
-          continue;  // a fine cell of the neighbouring fine face
-        dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
-      } else {
-        dcell = dst_cell0 + r * dstride;
+      for (int r = 0; r < R; ++r) {
+        int dcell;
+        if (DIR == 0) {
+          const int g = DIM == 3 ? r / 9 : r / 3, tb = DIM == 3 ? (r / 3) % 3 : r % 3;
+          const int tc = DIM == 3 ? r % 3 : 0;
+          if (decltype(check)::value &&
+              ((unsigned)(dst_b + tb) >= (unsigned)p ||
+               (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p)))
+            continue;
+          dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
+        } else {
+          dcell = dst_cell0 + r * dstride;
+        }
+        // Streaming (non-temporal) stores: the written halo is not re-read by
+        // this launch.
+        __builtin_nontemporal_store(T(r == COPY ? copy_val : acc[r]), &dp[(int64_t)dcell * U + u]);
       }
-      // Streaming (non-temporal) stores: the written halo is not re-read by
-      // this launch, and keeping it out of L2 preserves the source
-      // footprints that neighbouring anchors of the same face re-read.
-      __builtin_nontemporal_store(T(r == COPY ? copy_val : acc[r]), &dp[(int64_t)dcell * U + u]);
-    }
+    };
+    if (full)
+      store_rows(std::false_type{});
+    else
+      store_rows(std::true_type{});
   }
 }
 
@@ -350,16 +363,27 @@ __device__ __forceinline__ void mfma_item(
     const int u = u0 + lane;
     if (u < U) {
       const float xc = COPY >= 0 ? sp[(int64_t)copy_cell * U + u] : 0.0f;
+      // Anchors whose fine cells all belong to this fine face (every anchor
+      // when 3 divides p) store straight through; the others skip the cells
+      // of the neighbouring fine face.
+      const bool full = dst_b >= 0 && dst_b + 2 < p && (DIM == 2 || (dst_c >= 0 && dst_c + 2 < p));
+      auto store_rows = [&](auto check) {
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int g = DIM == 3 ? m / 9 : m / 3, tb = DIM == 3 ? (m / 3) % 3 : m % 3;
-        const int tc = DIM == 3 ? m % 3 : 0;
-        if ((unsigned)(dst_b + tb) >= (unsigned)p ||
-            (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p))
-          continue;  // a fine cell of the neighbouring fine face
-        const int dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
-        __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
-      }
+        for (int m = 0; m < R; ++m) {
+          const int g = DIM == 3 ? m / 9 : m / 3, tb = DIM == 3 ? (m / 3) % 3 : m % 3;
+          const int tc = DIM == 3 ? m % 3 : 0;
+          if (decltype(check)::value &&
+              ((unsigned)(dst_b + tb) >= (unsigned)p ||
+               (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p)))
+            continue;
+          const int dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
+          __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
+        }
+      };
+      if (full)
+        store_rows(std::false_type{});
+      else
+        store_rows(std::true_type{});
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
