@@ -320,6 +320,10 @@ int copy_patch_halos(int p, int k, int64_t n_pairs, const int8_t* axis,
  * (Section 2: halos are refreshed before the compute kernel).  Without it,
  * all batches must be independent (no face writes what another reads). */
 #define FT_PLAN_RESTRICT_FIRST 1
+/* FT_PLAN_PATCHES: every batch addresses patches (the layout of the patch
+ * calls above): coarse_offset / fine_offset are patch offsets and `coarse` /
+ * `fine` are patch pools, which may be the same array. */
+#define FT_PLAN_PATCHES 2
 
 typedef struct ft_plan ft_plan;
 typedef struct ft_graph ft_graph;

@@ -264,6 +264,7 @@ def transfer_version():
 # Plans and graphs
 # ---------------------------------------------------------------------------
 FT_PLAN_RESTRICT_FIRST = 1
+FT_PLAN_PATCHES = 2
 
 
 def pack_schedule(waves_per_block=4, blocks_per_cu=8, xcd_remap=0, heavy_first=0, persistent=1):

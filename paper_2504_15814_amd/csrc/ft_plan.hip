@@ -43,6 +43,8 @@ struct PlanSeg {
   int64_t item_end;  // one past its last work item
   int kind;
   int anchors;
+  int layout;  // kFaceBuffers, or kPatches (FT_PLAN_PATCHES)
+  int pad_;
 };
 
 // One work item of a plan segment, for one kind of operator.
@@ -60,11 +62,11 @@ __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const i
     constexpr int COPY = R >= 18 ? 13 : -1;
     if constexpr (MODE == 0)
       apply_item<0, R, 0, COPY, T, T, T>(
-          op, face, e, kFaceBuffers, S->orientation, S->subface, S->coarse_offset,
+          op, face, e, S->layout, S->orientation, S->subface, S->coarse_offset,
           S->fine_offset, U, coarse, coarse_elems, fine, fine_elems,
           (const T*)(sizeof(T) == 8 ? (const void*)cop->w64 : (const void*)cop->w32), S->errors);
     else
-      mfma_item<R, 0, MODE>(op, face, e, kFaceBuffers, wave, tile_all, S->orientation,
+      mfma_item<R, 0, MODE>(op, face, e, S->layout, wave, tile_all, S->orientation,
                             S->subface, S->coarse_offset, S->fine_offset, U, (const float*)coarse,
                             coarse_elems, (float*)fine, fine_elems, S->errors);
   } else {
@@ -72,7 +74,7 @@ __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const i
                           ? 1
                           : ((KIND == kRestrict2Inject || KIND == kRestrict2Plain) ? 2 : 3);
     constexpr int COPY = (KIND == kRestrict2Inject || KIND == kRestrict3Inject) ? 0 : -1;
-    apply_item<1, R, 0, COPY, T, double, double>(op, face, e, kFaceBuffers, S->orientation,
+    apply_item<1, R, 0, COPY, T, double, double>(op, face, e, S->layout, S->orientation,
                                                  S->subface, S->fine_offset, S->coarse_offset,
                                                  U, fine, fine_elems, coarse, coarse_elems,
                                                  cop->w64, S->errors);
@@ -267,6 +269,7 @@ int upload_tables(ft_plan* plan) {
       sgm.errors = b.op->d_errors;
       sgm.anchors = b.op->E * b.op->E;
       sgm.kind = plan_kind(b.op);
+      sgm.layout = (plan->flags & FT_PLAN_PATCHES) ? ft::kPatches : ft::kFaceBuffers;
       sgm.item0 = item;
       item += b.n_faces * sgm.anchors;
       sgm.item_end = item;
@@ -337,8 +340,13 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
   if (!batches || n_batches < 1) return pfail(FT_ERR_INVALID, "need at least one batch");
   if (unknowns < 1 || unknowns > 4096) return pfail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
   if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return pfail(FT_ERR_UNSUPPORTED, "unsupported dtype");
-  if (flags & ~FT_PLAN_RESTRICT_FIRST) return pfail(FT_ERR_INVALID, "unknown flags");
-  if (!coarse || !fine || coarse_elems < 0 || fine_elems < 0 || coarse == fine)
+  if (flags & ~(FT_PLAN_RESTRICT_FIRST | FT_PLAN_PATCHES))
+    return pfail(FT_ERR_INVALID, "unknown flags");
+  // Face buffers: one array for coarse and fine would let a face overwrite
+  // what it reads.  Patches: reads are face views, writes halos of other
+  // faces, so one pool may hold both.
+  if (!coarse || !fine || coarse_elems < 0 || fine_elems < 0 ||
+      (coarse == fine && !(flags & FT_PLAN_PATCHES)))
     return pfail(FT_ERR_INVALID, "bad coarse / fine buffers");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);

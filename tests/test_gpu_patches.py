@@ -366,3 +366,72 @@ def test_patches_halo_depth_one(p, U):
     torch.cuda.synchronize()
     want = opt.copy_patch_halos(p, k, axis.cpu().numpy(), lower.cpu().numpy(), upper.cpu().numpy(), U, npy(b.fine))
     assert np.array_equal(npy(pool), want)
+
+
+def _patch_mix(dev, dtype, one_pool=False):
+    """Three groups of patch transitions (p, k, scheme) = (9, 3, Taylor-3),
+    (6, 2, Taylor-2), (8, 3, d-linear) in shared pools, nine fine patches
+    per coarse face."""
+    groups = [(9, 3, oracle.TAYLOR3), (6, 2, oracle.TAYLOR2), (8, 3, oracle.DLINEAR)]
+    U = 13
+    parts = [patch_transitions(18, p, k, U, seed=700 + p, device=dev, dtype=dtype, faces_per_coarse=9)
+             for p, k, _ in groups]
+    coarse = torch.cat([b.coarse for b in parts])
+    fine = torch.cat([b.fine for b in parts])
+    c0 = f0 = 0
+    fshift = coarse.numel() if one_pool else 0
+    batches = []
+    for (p, k, scheme), b in zip(groups, parts):
+        co, fo = b.coarse_offset + c0, b.fine_offset + f0 + fshift
+        rop = api.build_transfer_operator(1, scheme, p, k)
+        iop = api.build_transfer_operator(0, scheme, p, k)
+        batches.append((rop, b.orientation, b.subface, co, fo))
+        batches.append((iop, b.orientation, b.subface, co, fo))
+        c0 += b.coarse.numel()
+        f0 += b.fine.numel()
+    if one_pool:
+        pool = torch.cat([coarse, fine])
+        return U, batches, pool, pool
+    return U, batches, coarse, fine
+
+
+@pytest.mark.parametrize("mode", [None, api.FT_F32, api.FT_F32_BF16X6])
+@pytest.mark.parametrize("one_pool", [False, True])
+def test_plan_on_patches_equals_per_batch_calls(mode, one_pool):
+    """FT_PLAN_PATCHES with FT_PLAN_RESTRICT_FIRST: one plan (two launches)
+    over mixed patch transitions equals the per-batch patch calls (all
+    restrictions, then all interpolations) bit for bit; coarse and fine may
+    share one pool."""
+    dev = require_gpu()
+    dtype = torch.float64 if mode is None else torch.float32
+    U, batches, coarse, fine = _patch_mix(dev, dtype, one_pool)
+    rc, rf = coarse.clone(), (None if one_pool else fine.clone())
+    rfine = rc if one_pool else rf
+    for op, o, s, co, fo in batches:
+        if op.direction == 1:
+            api.restrict_patches(op, o, s, co, fo, U, rfine, rc, mode=mode)
+    for op, o, s, co, fo in batches:
+        if op.direction == 0:
+            api.interpolate_patches(op, o, s, co, fo, U, rc, rfine, mode=mode)
+    pc = coarse.clone()
+    pf = pc if one_pool else fine.clone()
+    plan = api.build_transfer_plan(batches, U, pc, pf, mode=mode,
+                                   flags=api.FT_PLAN_RESTRICT_FIRST | api.FT_PLAN_PATCHES)
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(pc, rc) and torch.equal(pf, rfine)
+    for op, *_ in batches:
+        assert op.errors() == 0
+    # a captured graph of two steps equals two eager steps from the same start
+    flags = api.FT_PLAN_RESTRICT_FIRST | api.FT_PLAN_PATCHES
+    ec = coarse.clone()
+    ef = ec if one_pool else fine.clone()
+    eager = api.build_transfer_plan(batches, U, ec, ef, mode=mode, flags=flags)
+    eager.run()
+    eager.run()
+    gc = coarse.clone()
+    gf = gc if one_pool else fine.clone()
+    graph = api.build_transfer_plan(batches, U, gc, gf, mode=mode, flags=flags).capture(steps=2)
+    graph.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(gc, ec) and torch.equal(gf, ef)
