@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--patch-faces", type=int, default=6003,
                     help="fine patches in the fused patch-halo leg, rounded up to a multiple "
                          "of 9 (0 disables it)")
+    ap.add_argument("--mesh-patch-meshes", type=int, default=1,
+                    help="meshes whose transition zone runs as patches (0 disables the leg)")
     ap.add_argument("--faces-2d", type=int, default=200000,
                     help="two-dimensional faces in the 2D leg (0 disables it)")
     ap.add_argument("--no-reports", action="store_true",
@@ -319,6 +321,64 @@ def patches_leg(args, torch, api, wl):
             "alg_bytes": {"restrict_patches": rbytes, "interpolate_patches": ibytes}}
 
 
+def mesh_patches_leg(args, torch, api, wl):
+    """The transition zone of a synthetic AMR mesh as patches (workload 8,
+    Taylor-3, p=9, k=3, U=59): a step restricts every fine leaf into its
+    coarse leaf's halo and then interpolates every fine halo, in place in one
+    pool of patches.  FP64 per-call (two launches per step, eager), FP64 plan
+    over patches with all steps in one captured graph, and the float32
+    split-bfloat16 plan in a graph; error of one mixed step vs one FP64
+    step."""
+    mp = wl.mesh_patches(n_meshes=args.mesh_patch_meshes, device="cuda:0", dtype=torch.float64)
+    U, steps = mp.U, args.mesh_steps
+    rop = api.build_transfer_operator(api.FT_RESTRICT, 3, mp.p, mp.k)
+    iop = api.build_transfer_operator(api.FT_INTERPOLATE, 3, mp.p, mp.k)
+    d = (mp.orientation, mp.subface, mp.coarse_offset, mp.fine_offset)
+    produced = mp.n * (9 * mp.k + mp.k) * (mp.p // 3) ** 2 * U
+    pool64 = mp.pool
+    pool32 = pool64.float()
+
+    def step64():
+        api.restrict_patches(rop, *d, U, pool64, pool64)
+        api.interpolate_patches(iop, *d, U, pool64, pool64)
+
+    flags = api.FT_PLAN_RESTRICT_FIRST | api.FT_PLAN_PATCHES
+    plan32 = api.build_transfer_plan([(rop, *d), (iop, *d)], U, pool32, pool32, mode=api.FT_F32_BF16X6,
+                                     flags=flags)
+    step64()
+    plan32.run()
+    torch.cuda.synchronize()
+    err, scale = 0.0, float(pool64.abs().max())
+    for c0 in range(0, pool64.numel(), 1 << 28):
+        a = pool64[c0:c0 + (1 << 28)]
+        b = pool32[c0:c0 + (1 << 28)].double()
+        err = max(err, float((a - b).abs().max()))
+    ms64, _ = run_steps([("f64_step", step64)], args.steps, args.warmup, torch)
+    plan64 = api.build_transfer_plan([(rop, *d), (iop, *d)], U, pool64, pool64, flags=flags)
+    out = {"workload": f"transition zone of {args.mesh_patch_meshes} seeded 3-level AMR mesh(es) as patches "
+                       f"({mp.n_patches} patches of 9^3 cells with halo depth 3, one pool), Taylor-3, U=59, "
+                       "restrict then interpolate in place",
+           "hanging_faces": mp.n, "patches": mp.n_patches, "steps": steps,
+           "ghost_cell_unknowns_per_step": produced, "f64_eager_ms_per_step": ms64,
+           "mixed_max_rel_err_one_step": err / scale}
+    for label, plan in (("f64_plan_graph", plan64), ("bf16x6_plan_graph", plan32)):
+        best, _ = plan.autotune(reps=3)
+        graph = plan.capture(steps=steps)
+        graph.launch()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        graph.launch()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[label] = {"ms_per_step": ms, "value": produced / (ms * 1e-3), "speedup_vs_f64_eager": ms64 / ms,
+                      "schedule": api.unpack_schedule(best)}
+        del graph
+    return out
+
+
 def faces_2d_leg(args, torch, api, wl):
     """Two-dimensional faces (p=9, k=3, U=59, FP64): the headline step's
     launches (three schemes, restrict then interpolate) on 2D face buffers."""
@@ -515,6 +575,10 @@ def main():
     if args.mesh_meshes > 0:
         result["mesh"] = mesh_leg(args, torch, api, wl)
         progress("mesh leg done")
+
+    if args.mesh_patch_meshes > 0:
+        result["mesh_patches"] = mesh_patches_leg(args, torch, api, wl)
+        progress("mesh patch leg done")
 
     if args.faces_2d > 0:
         result["faces_2d"] = faces_2d_leg(args, torch, api, wl)

@@ -25,6 +25,8 @@ Workloads (all seeds are 15814 + workload number; draw order is fixed below):
 6  hanging faces between patches with halos (see patch_transitions): 6,003
    fine patches of 9^3 cells, nine per coarse face, k = 3, U = 59.
 7  two-dimensional faces (see faces_2d): 200,000 faces, p = 9, k = 3, U = 59.
+8  the transition zone of one seeded mesh as one pool of patches (see
+   mesh_patches): 34,481 patches, 39,942 hanging faces, k = 3, U = 59.
 Faces sit on a grid of 9^3 coarse patches (h_c = 1/81, h_f = 1/243).
 """
 
@@ -630,3 +632,65 @@ def faces_2d(n_faces, p, k, U, seed, device="cpu", dtype=torch.float64):
     fine = torch.randn(n_faces * elems, generator=dgen, dtype=dtype, device=device)
     return FaceBatch(p, k, U, orient.to(device), sub.to(device), offs.to(device), offs.clone().to(device),
                      coarse, fine)
+
+
+# ---------------------------------------------------------------------------
+# Workload 8: the transition zone of a synthetic AMR mesh, as patches
+# ---------------------------------------------------------------------------
+@dataclass
+class MeshPatches:
+    """Patches (boxes of (p + 2k)^3 cells with face halos) of the leaves that
+    take part in a hanging face of amr_leaves meshes, all in one pool; face i
+    joins the coarse leaf at coarse_offset[i] to the fine leaf at
+    fine_offset[i] (element offsets into `pool`)."""
+
+    p: int
+    k: int
+    U: int
+    n_patches: int
+    orientation: torch.Tensor
+    subface: torch.Tensor
+    coarse_offset: torch.Tensor
+    fine_offset: torch.Tensor
+    pool: torch.Tensor
+
+    @property
+    def n(self):
+        return int(self.orientation.numel())
+
+
+def mesh_patches(n_meshes=1, p=9, k=3, U=59, device="cpu", dtype=torch.float64, seed=SEED_BASE + 8,
+                 base_level=3, chunk=256):
+    """The leaves adjacent to a resolution transition of n_meshes seeded
+    meshes (amr_leaves), one patch each, filled with bump fields sampled at
+    every cell centre of the box (interior and halos: the halos then hold the
+    values a halo refresh would produce)."""
+    gen = torch.Generator().manual_seed(seed)
+    fieldfn = bump_field(gen, U)
+    index, faces = {}, []
+    for m in range(n_meshes):
+        leaves = amr_leaves(seed * 7 + m, base_level)
+        for parent, leaf, o, s in sorted(hanging_faces(leaves)):
+            for key in ((m, parent), (m, leaf)):
+                if key not in index:
+                    index[key] = len(index)
+            faces.append((index[(m, parent)], index[(m, leaf)], o, s))
+    P = p + 2 * k
+    P3U = P ** 3 * U
+    n_patches = len(index)
+    pool = torch.zeros(n_patches * P3U, dtype=dtype, device=device)
+    keys = sorted(index, key=index.get)
+    g = torch.arange(P, dtype=torch.float64, device=device)
+    i2, i1, i0 = torch.meshgrid(g, g, g, indexing="ij")
+    local = (torch.stack([i0, i1, i2], dim=-1).reshape(-1, 3) - k + 0.5) / p  # in patch widths
+    for c0 in range(0, n_patches, chunk):
+        part = keys[c0:c0 + chunk]
+        corner = torch.tensor([[leaf[1 + ax] * 3.0 ** -leaf[0] for ax in range(3)] for _, leaf in part],
+                              dtype=torch.float64, device=device)
+        width = torch.tensor([3.0 ** -leaf[0] for _, leaf in part], dtype=torch.float64, device=device)
+        pos = corner[:, None, :] + local[None, :, :] * width[:, None, None]
+        vals = fieldfn(pos.reshape(-1, 3)).reshape(len(part), P3U)
+        pool[c0 * P3U:(c0 + len(part)) * P3U] = vals.reshape(-1).to(dtype)
+    t = torch.tensor(faces, dtype=torch.int64)
+    return MeshPatches(p, k, U, n_patches, t[:, 2].to(torch.int8).to(device), t[:, 3].to(torch.int8).to(device),
+                       (t[:, 0] * P3U).to(device), (t[:, 1] * P3U).to(device), pool)

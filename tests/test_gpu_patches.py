@@ -435,3 +435,42 @@ def test_plan_on_patches_equals_per_batch_calls(mode, one_pool):
     graph.launch()
     torch.cuda.synchronize()
     assert torch.equal(gc, ec) and torch.equal(gf, ef)
+
+
+def test_mesh_transition_zone_as_patches():
+    """A small synthetic AMR mesh (base level 2) as one pool of patches: the
+    restrict -> interpolate step through per-call patch launches equals the
+    FT_PLAN_PATCHES plan bit for bit, and sampled faces equal the oracle."""
+    from paper_2504_15814_amd import workloads as wl
+
+    dev = require_gpu()
+    mp = wl.mesh_patches(n_meshes=1, U=3, device=dev, base_level=2)
+    assert mp.n > 100
+    U, p, k = mp.U, mp.p, mp.k
+    rop = api.build_transfer_operator(1, oracle.TAYLOR3, p, k)
+    iop = api.build_transfer_operator(0, oracle.TAYLOR3, p, k)
+    d = (mp.orientation, mp.subface, mp.coarse_offset, mp.fine_offset)
+    a = mp.pool.clone()
+    api.restrict_patches(rop, *d, U, a, a)
+    api.interpolate_patches(iop, *d, U, a, a)
+    b = mp.pool.clone()
+    plan = api.build_transfer_plan([(rop, *d), (iop, *d)], U, b, b,
+                                   flags=api.FT_PLAN_RESTRICT_FIRST | api.FT_PLAN_PATCHES)
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert rop.errors() == 0 and iop.errors() == 0
+    # oracle on sampled faces: restriction of one face from the initial
+    # state writes only its own segment
+    P3U = (p + 2 * k) ** 3 * U
+    pool0 = mp.pool.cpu().numpy()
+    got = a.cpu().numpy()
+    o, s = mp.orientation.cpu().numpy(), mp.subface.cpu().numpy()
+    co, fo = mp.coarse_offset.cpu().numpy(), mp.fine_offset.cpu().numpy()
+    for i in (0, mp.n // 2, mp.n - 1):
+        fine = pool0[fo[i]:fo[i] + P3U]
+        coarse = pool0[co[i]:co[i] + P3U]
+        want = opt.restrict_patches(oracle.TAYLOR3, p, k, [o[i]], [s[i]], [0], [0], U, fine, coarse)
+        mask = want != coarse
+        seg = got[co[i]:co[i] + P3U]
+        assert np.abs(seg[mask] - want[mask]).max() <= 1e-12 * np.abs(want[mask]).max()
