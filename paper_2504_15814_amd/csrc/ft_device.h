@@ -46,6 +46,19 @@ __device__ __forceinline__ const FT_CONST P* cptr(const P* p) {
   return (const FT_CONST P*)p;
 }
 
+// Logical block number.  Hardware dispatches block i to XCD i % 8; with
+// xcd_remap each XCD receives a contiguous range of logical blocks instead,
+// so neighbouring anchors of one face share that XCD's L2.
+__device__ inline int64_t logical_block(int xcd_remap) {
+  const int64_t b = blockIdx.x;
+  if (!xcd_remap) return b;
+  const int64_t nb = gridDim.x;
+  const int64_t per = nb / 8;
+  const int64_t full = per * 8;
+  if (b >= full) return b;
+  return (b % 8) * per + b / 8;
+}
+
 // DIR 0: interpolation (src = coarse, dst = fine).  DIR 1: restriction
 // (src = fine, dst = coarse).  R rows per anchor; EC anchors per axis (0 = read
 // from the operator); COPY is the exact-copy row (its source is stencil entry

@@ -28,8 +28,9 @@ struct LaunchArgs {
 struct LaunchConfig {
   int waves_per_block = 4;  // 1..4
   // Consecutive blocks on one XCD, so that the anchors of a face share one
-  // L2: halves the interpolation's L2 misses (Taylor-3: 1.49 -> 0.75 GB per
-  // 20,000 faces) and gives restriction ~2 %.
+  // L2: halves the float64 interpolation's L2 misses (Taylor-3: 1.49 -> 0.75
+  // GB per 20,000 faces) and gives restriction ~2 %; not used for float32
+  // interpolation, which it slows down.
   int xcd_remap = 1;
 };
 

@@ -20,19 +20,6 @@ struct Geometry {
   int layout;     // kFaceBuffers or kPatches
 };
 
-__device__ inline int64_t logical_block(int xcd_remap) {
-  const int64_t b = blockIdx.x;
-  if (!xcd_remap) return b;
-  // Hardware dispatches block i to XCD i % 8.  Renumber so that each XCD
-  // receives a contiguous range of logical blocks (neighbouring anchors of
-  // one face then share that XCD's L2).
-  const int64_t nb = gridDim.x;
-  const int64_t per = nb / 8;
-  const int64_t full = per * 8;
-  if (b >= full) return b;
-  return (b % 8) * per + b / 8;
-}
-
 template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W, int DIM>
 __global__ __launch_bounds__(256) void apply_kernel(
     const DevOp* __restrict__ op, const Geometry geo, const int8_t* __restrict__ orientation,
@@ -132,7 +119,10 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
   g.n_faces = la.n_faces;
   g.anchors = op->dim == 3 ? op->E * op->E : op->E;
   g.waves_per_block = cfg.waves_per_block;
-  g.xcd_remap = cfg.xcd_remap;
+  // XCD-contiguous numbering: restriction 2.5 % faster, float64
+  // interpolation unchanged (half the L2 misses), float32 interpolation 3-5 %
+  // slower.
+  g.xcd_remap = (op->direction == FT_INTERPOLATE && la.dtype != FT_F64) ? 0 : cfg.xcd_remap;
   g.layout = la.layout;
   if (la.dtype == FT_F64) return launch_typed<double, double>(op, g, la, stream);
   // FT_F32 and (for restriction) the split-bfloat16 modes: float32 storage.
