@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--faces", type=int, default=20000)
-    ap.add_argument("--cpu-faces", type=int, default=20000,
+    ap.add_argument("--cpu-faces", type=int, default=8000,
                     help="faces in the oracle's CPU-baseline sample (0 disables it)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--batched-faces", type=int, default=50000,
@@ -422,8 +422,11 @@ def faces_2d_leg(args, torch, api, wl):
 def cpu_baseline(batch, n_faces, torch):
     """The FP64 oracle on the host, on the first n_faces faces of the same
     batch; operators are built before timing (the paper times repeated calls
-    without reallocation)."""
-    import numpy as np
+    without reallocation) and their build is timed separately.  Median of
+    three runs with the host BLAS threads, plus one single-thread run on a
+    tenth of the sample."""
+    import statistics
+
     import threadpoolctl
 
     import oracle
@@ -436,25 +439,45 @@ def cpu_baseline(batch, n_faces, torch):
     s = batch.subface[:n_faces].cpu().numpy()
     co = batch.coarse_offset[:n_faces].cpu().numpy()
     fo = batch.fine_offset[:n_faces].cpu().numpy()
+    oracle.clear_operator_cache()
+    t0 = time.perf_counter()
     for scheme in (1, 2, 3):
         for oo in range(6):
             for ss in range(9):
                 oracle.interpolation_operator(scheme, p, k, oo, ss)
                 oracle.restriction_operator(scheme, p, k, oo, ss)
+    build_s = time.perf_counter() - t0
     threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=1)
-    t0 = time.perf_counter()
-    for scheme in (1, 2, 3):
-        oracle.restrict_faces(scheme, p, k, o, s, co, fo, U, fine, coarse)
-        oracle.interpolate_faces(scheme, p, k, o, s, co, fo, U, coarse, fine)
-    dt = time.perf_counter() - t0
-    produced = 3 * n_faces * (9 * k * (p // 3) ** 2 + k * (p // 3) ** 2) * U
+
+    def run(n):
+        t = time.perf_counter()
+        for scheme in (1, 2, 3):
+            oracle.restrict_faces(scheme, p, k, o[:n], s[:n], co[:n], fo[:n], U, fine, coarse)
+            oracle.interpolate_faces(scheme, p, k, o[:n], s[:n], co[:n], fo[:n], U, coarse, fine)
+        return time.perf_counter() - t
+
+    per_face = 3 * (9 * k * (p // 3) ** 2 + k * (p // 3) ** 2) * U
+    dt = statistics.median(run(n_faces) for _ in range(3))
+    n1 = max(1, n_faces // 10)
+    with threadpoolctl.threadpool_limits(1):
+        dt1 = run(n1)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
-        "value": produced / dt,
+        "value": per_face * n_faces / dt,
         "unit": "ghost-cell-unknowns/s",
         "cores": int(threads),
         "kind": "oracle",
         "sample": f"first {n_faces} of {batch.n} faces, all 3 schemes x restrict+interpolate, "
-                  f"{dt:.1f} s wall on the host",
+                  f"median of 3 runs {dt:.1f} s wall with {threads} BLAS threads",
+        "single_thread_value": per_face * n1 / dt1,
+        "single_thread_sample": f"first {n1} faces, {dt1:.1f} s wall",
+        "operator_build_s": build_s,
+        "host": {"cpu": cpu_model, "nproc": os.cpu_count()},
     }
 
 
