@@ -38,21 +38,28 @@ def _run(cmd, verbose):
     return res
 
 
-def build(verbose=False):
-    """Compile every source and link the shared library; returns its path."""
+def build(verbose=False, jobs=None):
+    """Compile every source (in parallel, `jobs` at a time) and link the
+    shared library; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
+
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in DEVICE_SOURCES:
         obj = os.path.join(obj_dir, src + ".o")
-        _run([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *NO_PACKED_FP32, "-c",
-              os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *NO_PACKED_FP32, "-c",
+                     os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(obj_dir, src + ".o")
-        _run([HIPCC, *COMMON, *NO_PACKED_FP32, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([HIPCC, *COMMON, *NO_PACKED_FP32, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 8)
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        for fut in [pool.submit(_run, c, verbose) for c in cmds]:
+            fut.result()
     tmp = lib_path() + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, lib_path())
