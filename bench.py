@@ -214,12 +214,21 @@ def mesh_leg(args, torch, api, wl):
     ms64, _ = run_steps([("f64_step", step64)], steps, args.warmup, torch)
 
     c32, f32 = mf.coarse.float(), mf.fine.float()
+    # FP64 step on the float32-rounded inputs: the error of the mixed
+    # arithmetic alone (the end-to-end error also carries the rounding of the
+    # stored inputs, amplified by the restriction's extrapolation rows)
+    rc_c, rc_f = c32.double(), f32.double()
+    api.restrict_faces(rop, *d, U, rc_f, rc_c)
+    api.interpolate_faces(iop, *d, U, rc_c, rc_f)
     plan = api.build_transfer_plan([(rop, *d), (iop, *d)], U, c32, f32, mode=api.FT_F32_BF16X6,
                                    flags=api.FT_PLAN_RESTRICT_FIRST)
     plan.run()
     torch.cuda.synchronize()
     err = max(float((c32.double() - ref1_c).abs().max() / ref1_c.abs().max()),
               float((f32.double() - ref1_f).abs().max() / ref1_f.abs().max()))
+    kerr = max(float((c32.double() - rc_c).abs().max() / rc_c.abs().max()),
+               float((f32.double() - rc_f).abs().max() / rc_f.abs().max()))
+    del rc_c, rc_f
     best, _ = plan.autotune(reps=3)
     graph = plan.capture(steps=steps)
     graph.launch()
@@ -239,6 +248,7 @@ def mesh_leg(args, torch, api, wl):
             "f64_ms_per_step": ms64, "mixed_graph_ms_per_step": ms_mixed,
             "mixed_value": produced / (ms_mixed * 1e-3), "f64_value": produced / (ms64 * 1e-3),
             "speedup": ms64 / ms_mixed, "mixed_max_rel_err_one_step": err,
+            "mixed_kernel_max_rel_err_one_step": kerr,
             "schedule": api.unpack_schedule(best)}
 
 
@@ -337,6 +347,7 @@ def mesh_patches_leg(args, torch, api, wl):
     produced = mp.n * (9 * mp.k + mp.k) * (mp.p // 3) ** 2 * U
     pool64 = mp.pool
     pool32 = pool64.float()
+    rounded = pool32.double()  # FP64 step on the float32-rounded inputs (kernel error)
 
     def step64():
         api.restrict_patches(rop, *d, U, pool64, pool64)
@@ -346,13 +357,18 @@ def mesh_patches_leg(args, torch, api, wl):
     plan32 = api.build_transfer_plan([(rop, *d), (iop, *d)], U, pool32, pool32, mode=api.FT_F32_BF16X6,
                                      flags=flags)
     step64()
+    api.restrict_patches(rop, *d, U, rounded, rounded)
+    api.interpolate_patches(iop, *d, U, rounded, rounded)
     plan32.run()
     torch.cuda.synchronize()
-    err, scale = 0.0, float(pool64.abs().max())
+    err, kerr, scale = 0.0, 0.0, float(pool64.abs().max())
     for c0 in range(0, pool64.numel(), 1 << 28):
         a = pool64[c0:c0 + (1 << 28)]
+        r = rounded[c0:c0 + (1 << 28)]
         b = pool32[c0:c0 + (1 << 28)].double()
         err = max(err, float((a - b).abs().max()))
+        kerr = max(kerr, float((r - b).abs().max()))
+    del rounded
     ms64, _ = run_steps([("f64_step", step64)], args.steps, args.warmup, torch)
     plan64 = api.build_transfer_plan([(rop, *d), (iop, *d)], U, pool64, pool64, flags=flags)
     out = {"workload": f"transition zone of {args.mesh_patch_meshes} seeded 3-level AMR mesh(es) as patches "
@@ -360,7 +376,7 @@ def mesh_patches_leg(args, torch, api, wl):
                        "restrict then interpolate in place",
            "hanging_faces": mp.n, "patches": mp.n_patches, "steps": steps,
            "ghost_cell_unknowns_per_step": produced, "f64_eager_ms_per_step": ms64,
-           "mixed_max_rel_err_one_step": err / scale}
+           "mixed_max_rel_err_one_step": err / scale, "mixed_kernel_max_rel_err_one_step": kerr / scale}
     for label, plan in (("f64_plan_graph", plan64), ("bf16x6_plan_graph", plan32)):
         best, _ = plan.autotune(reps=3)
         graph = plan.capture(steps=steps)
@@ -570,17 +586,35 @@ def main():
         # Reference outputs of the last FP64 scheme (Taylor-3) for error reports.
         ref_c, ref_f = outs64[0].clone(), outs64[1].clone()
         del launches, outs64
+        # The same FP64 Taylor-3 step on the float32-rounded inputs: the
+        # difference to it is the error of the float32 arithmetic alone (the
+        # restriction's extrapolation rows amplify the input rounding).
+        rin_c, rin_f = batch.coarse.float().double(), batch.fine.float().double()
+        rref_c, rref_f = rin_c.clone(), rin_f.clone()
+        d = (batch.orientation, batch.subface, batch.coarse_offset, batch.fine_offset)
+        rop3 = api.build_transfer_operator(api.FT_RESTRICT, 3, p, k)
+        iop3 = api.build_transfer_operator(api.FT_INTERPOLATE, 3, p, k)
+        api.restrict_faces(rop3, *d, U, rin_f, rref_c)
+        api.interpolate_faces(iop3, *d, U, rin_c, rref_f)
+        torch.cuda.synchronize()
+        del rin_c, rin_f, rop3, iop3
+
+        def rel_errors(got, ref):
+            g = got.view(-1, U).double()
+            rr = ref.view(-1, U)
+            emax = (g - rr).abs().amax(dim=0) / rr.abs().amax(dim=0)
+            erms = (g - rr).pow(2).mean(dim=0).sqrt() / rr.pow(2).mean(dim=0).sqrt()
+            return {"max_rel": float(emax.max()), "rms_rel": float(erms.max())}
+
         result["mixed"] = {}
         for label, mode in (("f32", api.FT_F32), ("bf16x3", api.FT_F32_BF16X3), ("bf16x6", api.FT_F32_BF16X6)):
             mlaunches, mops, mouts = make_launches(torch.float32, mode)
             mms, mkern = run_steps(mlaunches, args.steps, args.warmup, torch)
-            errs = {}
-            for nm, got, ref in (("interpolate_taylor3", mouts[1], ref_f), ("restrict_taylor3", mouts[0], ref_c)):
-                g = got.view(-1, U).double()
-                rr = ref.view(-1, U)
-                emax = (g - rr).abs().amax(dim=0) / rr.abs().amax(dim=0)
-                erms = (g - rr).pow(2).mean(dim=0).sqrt() / rr.pow(2).mean(dim=0).sqrt()
-                errs[nm] = {"max_rel": float(emax.max()), "rms_rel": float(erms.max())}
+            errs, kerrs = {}, {}
+            for nm, got, ref, rref in (("interpolate_taylor3", mouts[1], ref_f, rref_f),
+                                       ("restrict_taylor3", mouts[0], ref_c, rref_c)):
+                errs[nm] = rel_errors(got, ref)
+                kerrs[nm] = rel_errors(got, rref)
             progress(f"float32 {label} step: {mms:.3f} ms")
             result["mixed"][label] = {
                 "value": produced / (mms * 1e-3),
@@ -588,6 +622,7 @@ def main():
                 "speedup_vs_f64": ms / mms,
                 "kernels_ms": {kk: round(v, 4) for kk, v in mkern.items()},
                 "err_vs_f64_gpu": errs,
+                "err_vs_f64_gpu_on_rounded_inputs": kerrs,
             }
             del mlaunches, mops, mouts
 
