@@ -219,11 +219,10 @@ __device__ __forceinline__ void apply_item(
 }
 
 // Float32 interpolation on the matrix cores (see the file comment).
-// tile_all: the block's LDS transpose tiles, one per wave (wave_slot < 4).
 template <int R, int EC, int TERMS, int DIM = 3>
 __device__ __forceinline__ void mfma_item(
     const DevOp* __restrict__ op_, const int face, const int e, const int layout,
-    const int wave_slot, float (*tile_all)[32][65], const int8_t* __restrict__ orientation_,
+    const int8_t* __restrict__ orientation_,
     const int8_t* __restrict__ subface_, const int64_t* __restrict__ src_offset_,
     const int64_t* __restrict__ dst_offset_, const int U, const float* __restrict__ src,
     const int64_t src_elems, float* __restrict__ dst, const int64_t dst_elems,
@@ -237,7 +236,6 @@ __device__ __forceinline__ void mfma_item(
   // the coarse centre itself when k >= 2; with k = 1 no row is a copy.
   constexpr int COPY = DIM == 3 ? (R >= 18 ? 13 : -1) : (R >= 6 ? 4 : -1);
   const int lane = threadIdx.x & 63;
-  const int h = lane >> 5, col = lane & 31;
   const int E = EC > 0 ? EC : op->E;
   const int eb = DIM == 3 ? e % E : e, ec = DIM == 3 ? e / E : 0;
   const int p = op->p, k = op->k;
@@ -292,9 +290,6 @@ __device__ __forceinline__ void mfma_item(
 
   const float* __restrict__ sp = src + so;
   float* __restrict__ dp = dst + dof;
-  // Per-wave LDS tile for transposing the accumulators: rows x 64 unknowns
-  // (+1 pad); stores then write whole cells with lanes over unknowns.
-  float(*tile)[65] = tile_all[wave_slot];
   for (int u0 = 0; u0 < U; u0 += 64) {
     // Lanes run over 64 unknowns: every stencil cell is one coalesced load.
     // The B operands of the two 32-unknown tiles are then formed in
@@ -363,16 +358,19 @@ __device__ __forceinline__ void mfma_item(
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2, b0b, acc1, 0, 0, 0);
       }
     }
+    // In lane 32 h + col, accumulator v of tile t holds row 8 (v / 4) + 4 h +
+    // v % 4 for unknown u0 + 32 t + col.  v_permlane32_swap of (acc0[v], acc1[v]) leaves the
+    // h = 0 row in the first result and the h = 1 row in the second, each with
+    // lanes over the 64 unknowns u0 + lane: whole cells, without LDS.
+    float rows[32];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int m = 8 * (v / 4) + 4 * h + (v % 4);
-      tile[m][col] = acc0[v];
-      tile[m][32 + col] = acc1[v];
+      const int m = 8 * (v / 4) + (v % 4);
+      const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc0[v]),
+                                                       __float_as_uint(acc1[v]), false, false);
+      rows[m] = __uint_as_float(sw[0]);
+      rows[m + 4] = __uint_as_float(sw[1]);
     }
-    // The tile is private to this wave: order its LDS writes before the reads.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int u = u0 + lane;
     if (u < U) {
       const float xc = COPY >= 0 ? sp[(int64_t)copy_cell * U + u] : 0.0f;
@@ -390,7 +388,7 @@ __device__ __forceinline__ void mfma_item(
                (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p)))
             continue;
           const int dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
-          __builtin_nontemporal_store(m == COPY ? xc : tile[m][lane], &dp[(int64_t)dcell * U + u]);
+          __builtin_nontemporal_store(m == COPY ? xc : rows[m], &dp[(int64_t)dcell * U + u]);
         }
       };
       if (full)
@@ -398,9 +396,6 @@ __device__ __forceinline__ void mfma_item(
       else
         store_rows(std::true_type{});
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 

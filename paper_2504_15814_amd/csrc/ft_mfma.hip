@@ -18,16 +18,14 @@ __global__ __launch_bounds__(256) void interp_mfma_kernel(
     const int64_t* __restrict__ src_offset, const int64_t* __restrict__ dst_offset, const int U,
     const float* __restrict__ src, const int64_t src_elems, float* __restrict__ dst,
     const int64_t dst_elems, int* __restrict__ errors, const int layout, const int xcd_remap) {
-  __shared__ float tile_all[4][32][65];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int E = EC > 0 ? EC : op->E;
   const int anchors = DIM == 3 ? E * E : E;
   const int item = (int)logical_block(xcd_remap) * waves_per_block + wave;
   const int face = item / anchors;
   if (face >= n_faces) return;
-  mfma_item<R, EC, TERMS, DIM>(op, face, item - face * anchors, layout, wave, tile_all, orientation,
-                          subface, src_offset, dst_offset, U, src, src_elems, dst, dst_elems,
-                          errors);
+  mfma_item<R, EC, TERMS, DIM>(op, face, item - face * anchors, layout, orientation, subface,
+                               src_offset, dst_offset, U, src, src_elems, dst, dst_elems, errors);
 }
 
 template <int R, int EC, int TERMS, int DIM = 3>

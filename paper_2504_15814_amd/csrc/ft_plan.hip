@@ -50,9 +50,9 @@ struct PlanSeg {
 // One work item of a plan segment, for one kind of operator.
 template <typename T, int MODE, int KIND>
 __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const int face_, const int e_,
-                                       const int wave, float (*tile_all)[32][65], const int U,
-                                       T* __restrict__ coarse, const int64_t coarse_elems,
-                                       T* __restrict__ fine, const int64_t fine_elems) {
+                                       const int U, T* __restrict__ coarse,
+                                       const int64_t coarse_elems, T* __restrict__ fine,
+                                       const int64_t fine_elems) {
   const int face = __builtin_amdgcn_readfirstlane(face_);
   const int e = __builtin_amdgcn_readfirstlane(e_);
   const DevOp* __restrict__ op = S->op;
@@ -66,8 +66,8 @@ __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const i
           S->fine_offset, U, coarse, coarse_elems, fine, fine_elems,
           (const T*)(sizeof(T) == 8 ? (const void*)cop->w64 : (const void*)cop->w32), S->errors);
     else
-      mfma_item<R, 0, MODE>(op, face, e, S->layout, wave, tile_all, S->orientation,
-                            S->subface, S->coarse_offset, S->fine_offset, U, (const float*)coarse,
+      mfma_item<R, 0, MODE>(op, face, e, S->layout, S->orientation, S->subface,
+                            S->coarse_offset, S->fine_offset, U, (const float*)coarse,
                             coarse_elems, (float*)fine, fine_elems, S->errors);
   } else {
     constexpr int R = KIND == kRestrict1Plain
@@ -90,7 +90,6 @@ __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ s
                                                    const int remap, const int U,
                                                    T* __restrict__ coarse, const int64_t coarse_elems,
                                                    T* __restrict__ fine, const int64_t fine_elems) {
-  __shared__ float tile_all[MODE ? 4 : 1][32][65];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int64_t b = blockIdx.x;
   if (remap) {
@@ -115,8 +114,8 @@ __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ s
   for (int64_t it = first; it < item_end; it += stride) {                                      \
     const int local = (int)(it - item0); /* segments hold < 2^31 items */                      \
     const int face = local / anchors;                                                          \
-    plan_item<T, MODE, KIND>(S, face, local - face * anchors, wave, tile_all, U, coarse,       \
-                             coarse_elems, fine, fine_elems);                                  \
+    plan_item<T, MODE, KIND>(S, face, local - face * anchors, U, coarse, coarse_elems, fine,   \
+                             fine_elems);                                                      \
   }                                                                                            \
   break;
       case kInterp18: FT_PLAN_LOOP(kInterp18)
@@ -144,7 +143,6 @@ __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restric
                                                         const int64_t coarse_elems,
                                                         T* __restrict__ fine,
                                                         const int64_t fine_elems) {
-  __shared__ float tile_all[MODE ? 4 : 1][32][65];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int64_t b = blockIdx.x;
   if (remap) {
@@ -166,14 +164,14 @@ __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restric
   const int face = local / anchors;
   const int e = local - face * anchors;
   switch (S->kind) {
-    case kInterp18: plan_item<T, MODE, kInterp18>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kInterp27: plan_item<T, MODE, kInterp27>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict2Inject: plan_item<T, MODE, kRestrict2Inject>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict2Plain: plan_item<T, MODE, kRestrict2Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict3Inject: plan_item<T, MODE, kRestrict3Inject>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kInterp9: plan_item<T, MODE, kInterp9>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict1Plain: plan_item<T, MODE, kRestrict1Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
-    default: plan_item<T, MODE, kRestrict3Plain>(S, face, e, wave, tile_all, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp18: plan_item<T, MODE, kInterp18>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp27: plan_item<T, MODE, kInterp27>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict2Inject: plan_item<T, MODE, kRestrict2Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict2Plain: plan_item<T, MODE, kRestrict2Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict3Inject: plan_item<T, MODE, kRestrict3Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp9: plan_item<T, MODE, kInterp9>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict1Plain: plan_item<T, MODE, kRestrict1Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    default: plan_item<T, MODE, kRestrict3Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
   }
 }
 
