@@ -187,6 +187,7 @@ struct ft_plan {
   ft::PlanSeg* d_segs[2] = {nullptr, nullptr};
   int nseg[2] = {0, 0};
   int64_t total[2] = {0, 0};
+  bool interp[2] = {false, false};  // the phase holds interpolation segments
 };
 
 struct ft_graph {
@@ -235,6 +236,7 @@ void free_tables(ft_plan* plan) {
     plan->d_segs[ph] = nullptr;
     plan->nseg[ph] = 0;
     plan->total[ph] = 0;
+    plan->interp[ph] = false;
   }
 }
 
@@ -272,6 +274,7 @@ int upload_tables(ft_plan* plan) {
       item += b.n_faces * sgm.anchors;
       sgm.item_end = item;
       segs.push_back(sgm);
+      if (b.op->direction == FT_INTERPOLATE) plan->interp[ph] = true;
     }
     if (segs.empty()) continue;
     hipError_t e = hipMalloc(&plan->d_segs[ph], segs.size() * sizeof(ft::PlanSeg));
@@ -309,8 +312,12 @@ hipError_t launch_phase(const ft_plan* plan, int ph, hipStream_t stream) {
 int run_plan(const ft_plan* plan, hipStream_t stream) {
   for (int ph = 0; ph < 2; ++ph) {
     if (plan->total[ph] == 0) continue;
+    // Restriction items run the same vector-ALU body in every float32 mode; a
+    // phase without interpolation takes the kernel without matrix-core code
+    // (fewer registers, more waves per SIMD).
+    const int dtype = (plan->dtype != FT_F64 && !plan->interp[ph]) ? FT_F32 : plan->dtype;
     hipError_t e;
-    switch (plan->dtype) {
+    switch (dtype) {
       case FT_F64: e = launch_phase<double, 0>(plan, ph, stream); break;
       case FT_F32: e = launch_phase<float, 0>(plan, ph, stream); break;
       case FT_F32_BF16X3: e = launch_phase<float, 3>(plan, ph, stream); break;
