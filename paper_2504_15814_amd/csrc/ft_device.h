@@ -296,8 +296,8 @@ __device__ __forceinline__ void mfma_item(
     // registers: for a k-step (16 stencil points) each lane packs its 8 + 8
     // bfloat16 values, and v_permlane32_swap exchanges the upper half-wave of
     // the first 8 with the lower half-wave of the second 8, which yields
-    // B[8h + i][col] for unknowns u0 + col (tile 0) and u0 + 32 + col
-    // (tile 1).
+    // B[8h + i][col] in lane 32 h + col for unknowns u0 + col (tile 0) and
+    // u0 + 32 + col (tile 1).
     const int uu = min(u0 + lane, U - 1);
     f32x16 acc0 = {}, acc1 = {};
     for (int st_i = 0; st_i < nsteps; ++st_i) {

@@ -159,19 +159,24 @@ def _shared_face_setup(dev, dtype):
     return p, k, U, orient, sub, coff, foff, coarse, base.fine.clone()
 
 
-def test_restrict_first_plan_and_multi_step_graph(dev):
-    p, k, U, orient, sub, coff, foff, coarse0, fine0 = _shared_face_setup(dev, torch.float64)
+@pytest.mark.parametrize("dtype,mode", [(torch.float64, None), (torch.float32, api.FT_F32),
+                                        (torch.float32, api.FT_F32_BF16X3), (torch.float32, api.FT_F32_BF16X6)])
+def test_restrict_first_plan_and_multi_step_graph(dev, dtype, mode):
+    """Restriction phase then interpolation phase (in the float32 modes the
+    restriction-only phase runs the vector-ALU plan kernel): bitwise equal to
+    eager per-call steps in the same mode."""
+    p, k, U, orient, sub, coff, foff, coarse0, fine0 = _shared_face_setup(dev, dtype)
     rop = api.build_transfer_operator(1, 3, p, k)
     iop = api.build_transfer_operator(0, 3, p, k)
     # eager reference: restrict then interpolate, three steps
     rc, rf = coarse0.clone(), fine0.clone()
     for _ in range(3):
-        api.restrict_faces(rop, orient, sub, coff, foff, U, rf, rc)
-        api.interpolate_faces(iop, orient, sub, coff, foff, U, rc, rf)
+        api.restrict_faces(rop, orient, sub, coff, foff, U, rf, rc, mode=mode)
+        api.interpolate_faces(iop, orient, sub, coff, foff, U, rc, rf, mode=mode)
     torch.cuda.synchronize()
     coarse, fine = coarse0.clone(), fine0.clone()
     plan = api.build_transfer_plan([(iop, orient, sub, coff, foff), (rop, orient, sub, coff, foff)], U, coarse, fine,
-                                   flags=api.FT_PLAN_RESTRICT_FIRST)
+                                   mode=mode, flags=api.FT_PLAN_RESTRICT_FIRST)
     graph = plan.capture(steps=3)
     for rep in range(3):
         coarse.copy_(coarse0)
