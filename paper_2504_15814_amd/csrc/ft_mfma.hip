@@ -11,8 +11,11 @@
 
 namespace ft {
 
+// Six waves per SIMD: the accumulators then live in 80 VGPRs without spills
+// (the compiler's own choice, 58 VGPRs + 32 AGPRs, allows five; six-term
+// Taylor-3 interpolation 2-3 % faster, same-box A/B).
 template <int R, int EC, int TERMS, int DIM>
-__global__ __launch_bounds__(256) void interp_mfma_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void interp_mfma_kernel(
     const DevOp* __restrict__ op, const int64_t n_faces, const int waves_per_block,
     const int8_t* __restrict__ orientation, const int8_t* __restrict__ subface,
     const int64_t* __restrict__ src_offset, const int64_t* __restrict__ dst_offset, const int U,
