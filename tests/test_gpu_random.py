@@ -56,3 +56,49 @@ def test_random_configuration_f32(dev, case):
     assert np.array_equal(got[copy], want[copy])
     emax, _ = gh.rel_errors(got, want, mask, U)
     assert emax.max() < 1e-5
+
+
+def _patch_cases(n, seed=1581):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        scheme = int(rng.integers(1, 4))
+        k = int(rng.integers(1, 4)) if scheme == 1 else int(rng.integers(2, 4))
+        p = int(rng.integers(6, 14))
+        U = int(rng.choice([1, 5, 31, 59, 66]))
+        out.append((i, scheme, p, k, U))
+    return out
+
+
+PATCH_CASES = _patch_cases(10)
+
+
+@pytest.mark.parametrize("case", PATCH_CASES, ids=[f"c{c[0]}-s{c[1]}-p{c[2]}-k{c[3]}-U{c[4]}"
+                                                  for c in PATCH_CASES])
+def test_random_patch_transfer_f64(dev, case):
+    """Nine fine patches per coarse face, both directions, in place in the
+    patch boxes, against the oracle's patch functions."""
+    from oracle import patches as opt
+    from tests.test_gpu_patches import npy, written_halo_mask
+
+    i, scheme, p, k, U = case
+    b = wl.patch_transitions(18, p, k, U, seed=7000 + i, device=dev, faces_per_coarse=9)
+    o, s = b.orientation.cpu().numpy(), b.subface.cpu().numpy()
+    co, fo = b.coarse_offset.cpu().numpy(), b.fine_offset.cpu().numpy()
+    iop = api.build_transfer_operator(0, scheme, p, k)
+    rop = api.build_transfer_operator(1, scheme, p, k)
+    fine, coarse = b.fine.clone(), b.coarse.clone()
+    api.interpolate_patches(iop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, b.coarse, fine)
+    api.restrict_patches(rop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, b.fine, coarse)
+    torch.cuda.synchronize()
+    assert iop.errors() == 0 and rop.errors() == 0
+    want_f = opt.interpolate_patches(scheme, p, k, o, s, co, fo, U, npy(b.coarse), npy(b.fine))
+    want_c = opt.restrict_patches(scheme, p, k, o, s, co, fo, U, npy(b.fine), npy(b.coarse))
+    mask_f = written_halo_mask(p, k, U, o, fo, b.fine.numel())
+    mask_c = written_halo_mask(p, k, U, ((o.astype(np.int64) + 3) % 6)[::9], co[::9], b.coarse.numel())
+    for got, want, before, mask in ((npy(fine), want_f, npy(b.fine), mask_f),
+                                    (npy(coarse), want_c, npy(b.coarse), mask_c)):
+        assert np.array_equal(got[~mask], before[~mask])
+        d = np.abs(got[mask] - want[mask]).reshape(-1, U).max(axis=0)
+        scale = np.abs(want[mask]).reshape(-1, U).max(axis=0)
+        assert (d / scale).max() <= 1e-12
