@@ -439,9 +439,28 @@ def faces_2d_leg(args, torch, api, wl):
         kernels[name] = {"ms": round(kern[name], 4), "alg_bytes": nbytes,
                          "GB/s": round(nbytes / (kern[name] * 1e-3) / 1e9, 1)}
     produced = 3 * n * (3 * k * (p // 3) + k * (p // 3)) * U
+    # the same step in float32 storage with the six-term matrix-core form
+    c32, f32 = b.coarse.float(), b.fine.float()
+    c32_out, f32_out = c32.clone(), f32.clone()
+    launches32 = []
+    for scheme in (1, 2, 3):
+        rop, iop = ops[("restrict", scheme)], ops[("interpolate", scheme)]
+        launches32.append((f"restrict_{SCHEME_NAMES[scheme]}",
+                           lambda rop=rop: api.restrict_faces(rop, *d, U, f32, c32_out, mode=api.FT_F32_BF16X6)))
+        launches32.append((f"interpolate_{SCHEME_NAMES[scheme]}",
+                           lambda iop=iop: api.interpolate_faces(iop, *d, U, c32, f32_out,
+                                                                 mode=api.FT_F32_BF16X6)))
+    ms32, kern32 = run_steps(launches32, args.steps, args.warmup, torch)
+    errs = {}
+    for nm, got, ref in (("interpolate_taylor3", f32_out, f_out), ("restrict_taylor3", c32_out, c_out)):
+        g, rr = got.view(-1, U).double(), ref.view(-1, U)
+        errs[nm] = float(((g - rr).abs().amax(dim=0) / rr.abs().amax(dim=0)).max())
     return {"workload": f"{n} two-dimensional hanging faces, p=9, k=3, U=59, FP64; "
                         "dlinear+taylor2+taylor3; restrict+interpolate",
-            "ms_per_step": ms, "value": produced / (ms * 1e-3), "kernels": kernels}
+            "ms_per_step": ms, "value": produced / (ms * 1e-3), "kernels": kernels,
+            "bf16x6": {"ms_per_step": ms32, "value": produced / (ms32 * 1e-3), "speedup_vs_f64": ms / ms32,
+                       "kernels_ms": {kk: round(v, 4) for kk, v in kern32.items()},
+                       "max_rel_err_vs_f64": errs}}
 
 
 def cpu_baseline(batch, n_faces, torch):
