@@ -701,6 +701,7 @@ def main():
         torch.cuda.empty_cache()
         result["convergence"] = experiments.convergence(device=dev)
         result["operator_build"] = experiments.operator_build(device=dev)
+        result["runtime_vs_p"] = experiments.runtime_vs_p(device=dev)
         progress("reports done")
 
     print(json.dumps(result), flush=True)

@@ -11,6 +11,10 @@ operator_build()    Section 5.3: the paper builds the fit matrices on every
                     times one operator build (host fit + upload) against one
                     batched application, i.e. what a per-call construction
                     would add.
+runtime_vs_p()      Section 5.3: runtime of every scheme as the patch size p
+                    grows (halo depth 3, repeated calls without
+                    reallocation), per face and as algorithmic GB/s, both
+                    directions, including sizes that are not multiples of 3.
 
 Run as ``python -m paper_2504_15814_amd.experiments`` (one JSON object).
 """
@@ -136,9 +140,60 @@ def operator_build(device="cuda:0", p=9, k=3, n_faces=20000, U=59, reps=3):
     return {"p": p, "k": k, "unknowns": U, "faces": n_faces, "operators": out}
 
 
+def runtime_vs_p(device="cuda:0", sizes=(6, 7, 8, 9, 12, 15, 18, 21, 24, 27), k=3, U=59, reps=10,
+                 cells=20000 * 81):
+    """Mean time of one batched FP64 application per scheme, direction and
+    patch size; the batch holds about `cells` / p^2 faces (the same data
+    volume at every p), and the report gives microseconds per face and
+    algorithmic GB/s (distinct source cells with a nonzero weight plus
+    destination cells, per (orientation, subface), times U x 8 bytes)."""
+    out = {}
+    cg = torch.Generator().manual_seed(11)
+    for p in sizes:
+        n = max(64, cells // (p * p))
+        ncell = 2 * k * p * p
+        gen = torch.Generator(device=device).manual_seed(p)
+        src = torch.randn(n * ncell * U, generator=gen, dtype=torch.float64, device=device)
+        dst = torch.zeros_like(src)
+        o = torch.randint(0, 6, (n,), generator=cg).to(torch.int8)
+        s = torch.randint(0, 9, (n,), generator=cg).to(torch.int8)
+        counts = np.zeros((6, 9), dtype=np.int64)
+        np.add.at(counts, (o.numpy(), s.numpy()), 1)
+        o, s = o.to(device), s.to(device)
+        off = torch.arange(n, dtype=torch.int64, device=device) * ncell * U
+        row = {}
+        for scheme, name in SCHEMES.items():
+            for d, dname in ((0, "interpolate"), (1, "restrict")):
+                op = api.build_transfer_operator(d, scheme, p, k)
+                nbytes = 0
+                for oo in range(6):
+                    for ss in range(9):
+                        if counts[oo, ss]:
+                            r, c, v = op.segment(oo, ss)
+                            nbytes += int(counts[oo, ss]) * (len(np.unique(c[v != 0])) + len(np.unique(r))) * U * 8
+                fn = (lambda: api.interpolate_faces(op, o, s, off, off, U, src, dst)) if d == 0 else \
+                     (lambda: api.restrict_faces(op, o, s, off, off, U, src, dst))
+                fn()
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    fn()
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / reps
+                row[f"{dname}_{name}"] = {"ms": ms, "us_per_face": 1e3 * ms / n,
+                                          "alg_GB_per_s": nbytes / (ms * 1e-3) / 1e9}
+                op.destroy()
+        out[str(p)] = {"faces": n, **row}
+        del src, dst
+    return {"k": k, "unknowns": U, "sizes": out}
+
+
 def main():
     torch.cuda.set_device(0)
-    print(json.dumps({"convergence": convergence(), "operator_build": operator_build()}))
+    print(json.dumps({"convergence": convergence(), "operator_build": operator_build(),
+                      "runtime_vs_p": runtime_vs_p()}))
 
 
 if __name__ == "__main__":
