@@ -237,3 +237,39 @@ def test_plan_with_patch_sizes_not_multiples_of_three(dev):
                 got = pc_np[co[f]:co[f] + ncell * U].reshape(ncell, U)[rows]
             want = W @ x
             assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_full_size_uneven_mix_sampled(dev):
+    """50,000 faces of the uneven mix in one float32 plan launch (split
+    bfloat16, six terms) as the benchmark runs it: bitwise equal to the
+    per-batch calls, and two faces of every (direction, scheme, p, k) group
+    within the float32 bound of the oracle on the same inputs."""
+    mb = wl.workload4(n_faces=50000, device=dev, dtype=torch.float32)
+    ops = build_ops(mb)
+    rc, rf = per_batch_reference(mb, ops, api.FT_F32_BF16X6)
+    plan, pc, pf = run_plan(mb, ops, api.FT_F32_BF16X6)
+    plan.autotune(reps=1)
+    pc.copy_(mb.coarse)
+    pf.copy_(mb.fine)
+    plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(pc, rc) and torch.equal(pf, rf)
+    coarse_in = mb.coarse.double().cpu().numpy()
+    fine_in = mb.fine.double().cpu().numpy()
+    pc_np, pf_np = pc.double().cpu().numpy(), pf.double().cpu().numpy()
+    co, fo = mb.coarse_offset.cpu().numpy(), mb.fine_offset.cpu().numpy()
+    orient, sub = mb.orientation.cpu().numpy(), mb.subface.cpu().numpy()
+    U = mb.U
+    for (d, sch, p, k), idx in mb.groups().items():
+        for f in idx[:2].tolist():
+            rows, W = oracle.transfer_operator(d, sch, p, k, int(orient[f]), int(sub[f]))
+            ncell = 2 * k * p * p
+            if d == 0:
+                x = coarse_in[co[f]:co[f] + ncell * U].reshape(ncell, U)
+                got = pf_np[fo[f]:fo[f] + ncell * U].reshape(ncell, U)[rows]
+            else:
+                x = fine_in[fo[f]:fo[f] + ncell * U].reshape(ncell, U)
+                got = pc_np[co[f]:co[f] + ncell * U].reshape(ncell, U)[rows]
+            want = W @ x
+            bound = 21 * 2.0**-24 * (np.abs(W) @ np.abs(x)) + 2.0**-24 * np.abs(want)
+            assert np.all(np.abs(got - want) <= bound)
