@@ -103,3 +103,61 @@ def test_mesh_step_mixed_precision_plan(mesh):
     for got, ref in ((pc, ec), (pf, ef)):
         err = (got.double() - ref).abs().max() / ref.abs().max()
         assert err < 5e-5
+
+
+@pytest.fixture(scope="module")
+def mesh_full(dev):
+    return wl.workload5(n_meshes=3, device=dev)
+
+
+def test_full_size_mesh_step(mesh_full):
+    """The AMR-mesh workload at full size (three meshes, U = 59, Taylor-3) as
+    the benchmark runs it: the FP64 plan equals the eager step bit for bit and
+    matches the oracle on all nine subfaces of 12 coarse faces; the float32
+    six-term plan stays within 1e-6 (relative to the largest value) of the
+    FP64 step run on the same float32-rounded inputs."""
+    mf = mesh_full
+    U, E = mf.U, mf.face_elems
+    rop = api.build_transfer_operator(1, 3, mf.p, mf.k)
+    iop = api.build_transfer_operator(0, 3, mf.p, mf.k)
+    ec, ef = mf.coarse.clone(), mf.fine.clone()
+    step_eager(mf, rop, iop, ec, ef)
+    pc, pf = mf.coarse.clone(), mf.fine.clone()
+    make_plan(mf, rop, iop, pc, pf).run()
+    torch.cuda.synchronize()
+    assert torch.equal(pc, ec) and torch.equal(pf, ef)
+    assert rop.errors() == 0 and iop.errors() == 0
+    del pc, pf
+
+    # oracle on compact copies of 12 coarse faces and their nine fine faces
+    o, s = mf.orientation.cpu().numpy(), mf.subface.cpu().numpy()
+    co, fo = mf.coarse_offset.cpu().numpy(), mf.fine_offset.cpu().numpy()
+    picks = np.unique(co)[:: max(1, mf.n_coarse // 12)][:12]
+    faces = np.flatnonzero(np.isin(co, picks))
+    assert len(faces) == 9 * len(picks)
+    slot = {int(c): i for i, c in enumerate(picks)}
+    co_c = np.array([slot[int(co[f])] * E for f in faces], dtype=np.int64)
+    fo_c = np.arange(len(faces), dtype=np.int64) * E
+    coarse_c = np.concatenate([mf.coarse[int(c):int(c) + E].cpu().numpy() for c in picks])
+    fine_c = np.concatenate([mf.fine[int(fo[f]):int(fo[f]) + E].cpu().numpy() for f in faces])
+    c1 = oracle.restrict_faces(3, mf.p, mf.k, o[faces], s[faces], co_c, fo_c, U, fine_c, coarse_c)
+    f1 = oracle.interpolate_faces(3, mf.p, mf.k, o[faces], s[faces], co_c, fo_c, U, c1, fine_c)
+    for i, c in enumerate(picks):
+        got, want = ec[int(c):int(c) + E].cpu().numpy(), c1[i * E:(i + 1) * E]
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    for j, f in enumerate(faces):
+        got, want = ef[int(fo[f]):int(fo[f]) + E].cpu().numpy(), f1[j * E:(j + 1) * E]
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    del ec, ef
+
+    # float32 six-term plan against the FP64 step on the rounded inputs
+    c32, f32 = mf.coarse.float(), mf.fine.float()
+    rc, rf = c32.double(), f32.double()
+    make_plan(mf, rop, iop, c32, f32, mode=api.FT_F32_BF16X6).run()
+    step_eager(mf, rop, iop, rc, rf)
+    torch.cuda.synchronize()
+    for got, ref in ((c32, rc), (f32, rf)):
+        diff, scale = 0.0, float(ref.abs().max())
+        for c0 in range(0, ref.numel(), 1 << 27):
+            diff = max(diff, float((got[c0:c0 + (1 << 27)].double() - ref[c0:c0 + (1 << 27)]).abs().max()))
+        assert diff / scale < 1e-6, diff / scale
