@@ -47,6 +47,11 @@ def parse():
                     help="meshes whose transition zone runs as patches (0 disables the leg)")
     ap.add_argument("--faces-2d", type=int, default=200000,
                     help="two-dimensional faces in the 2D leg (0 disables it)")
+    ap.add_argument("--small-u-reps", type=int, default=200,
+                    help="calls per latency sample in the 64-face U=1 leg (0 disables it)")
+    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="file that receives every leg's full record (the headline is the "
+                         "last stdout line)")
     ap.add_argument("--no-reports", action="store_true",
                     help="skip the convergence and operator-build reports")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -471,6 +476,50 @@ def faces_2d_leg(args, torch, api, wl):
                        "max_rel_err_vs_f64": errs}}
 
 
+def small_u_leg(args, torch, api, wl):
+    """Latency of one call on a cache-resident batch: 64 hanging faces, p=9,
+    k=3, one unknown per cell (every orientation/subface pair present),
+    d-linear and Taylor-2, FP64, both directions.  `call_us`: mean GPU time
+    per call between events recorded around each call; `stream_us`: mean
+    time per call of `reps` calls issued back to back (host launch cost
+    included); `host_us`: host time to issue one call."""
+    b = wl.workload1(device="cuda:0")
+    d = (b.orientation, b.subface, b.coarse_offset, b.fine_offset)
+    reps = args.small_u_reps
+    out = {"workload": "64 faces, p=9, k=3, U=1, FP64 (cubic + sine field)", "reps": reps}
+    for scheme in (1, 2):
+        for direction in (api.FT_INTERPOLATE, api.FT_RESTRICT):
+            op = api.build_transfer_operator(direction, scheme, 9, 3)
+            c, f = b.coarse.clone(), b.fine.clone()
+            if direction == api.FT_INTERPOLATE:
+                fn = lambda op=op, c=c, f=f: api.interpolate_faces(op, *d, 1, b.coarse, f)
+            else:
+                fn = lambda op=op, c=c, f=f: api.restrict_faces(op, *d, 1, b.fine, c)
+            for _ in range(20):
+                fn()
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for a, z in ev:
+                a.record()
+                fn()
+                z.record()
+            torch.cuda.synchronize()
+            call_us = 1e3 * sum(a.elapsed_time(z) for a, z in ev) / reps
+            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            t1 = time.perf_counter()
+            z.record()
+            torch.cuda.synchronize()
+            name = ("interpolate_" if direction == api.FT_INTERPOLATE else "restrict_") + SCHEME_NAMES[scheme]
+            out[name] = {"call_us": round(call_us, 2), "stream_us": round(1e3 * a.elapsed_time(z) / reps, 2),
+                         "host_us": round(1e6 * (t1 - t0) / reps, 2)}
+    return out
+
+
 def cpu_baseline(batch, n_faces, torch):
     """The FP64 oracle on the host, on the first n_faces faces of the same
     batch; operators are built before timing (the paper times repeated calls
@@ -531,6 +580,92 @@ def cpu_baseline(batch, n_faces, torch):
         "operator_build_s": build_s,
         "host": {"cpu": cpu_model, "nproc": os.cpu_count()},
     }
+
+
+def _sig(x, digits=4):
+    """x rounded to `digits` significant digits (JSON-friendly)."""
+    return float(f"{x:.{digits}g}") if isinstance(x, (int, float)) and x is not None else x
+
+
+def headline(result, detail_path):
+    """The one-line record: the FP64 step of the benchmark workload with its
+    roofline and CPU baseline, plus a short summary of every other leg (the
+    full records are in the detail file)."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+            "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "hbm_frac_step")
+    h = {k_: result[k_] for k_ in keys if k_ in result}
+    h["kernels_ms_GBs"] = {k_: [v["ms"], v["GB/s"]] for k_, v in result["kernels"].items()}
+    if "cpu_baseline" in result:
+        cb = result["cpu_baseline"]
+        h["cpu_baseline"] = {k_: cb[k_] for k_ in ("value", "unit", "cores", "kind", "sample")}
+        h["cpu_baseline"]["single_thread_value"] = _sig(cb["single_thread_value"])
+    if "mixed" in result:
+        m = {"workload": "same faces, unknowns scaled 1e-6..1e3, float32 storage; err = worst "
+                         "per-unknown max relative error of Taylor-3 outputs vs the FP64 GPU path "
+                         "(e2e: on FP64 inputs; arith: on the float32-rounded inputs)"}
+        for label, v in result["mixed"].items():
+            if not isinstance(v, dict):
+                continue
+            e, ka = v["err_vs_f64_gpu"], v["err_vs_f64_gpu_on_rounded_inputs"]
+            m[label] = {"ms": _sig(v["ms_per_step"]), "speedup": _sig(v["speedup_vs_f64"], 3),
+                        "interp_err_e2e": _sig(e["interpolate_taylor3"]["max_rel"], 2),
+                        "restrict_err_e2e": _sig(e["restrict_taylor3"]["max_rel"], 2),
+                        "interp_err_arith": _sig(ka["interpolate_taylor3"]["max_rel"], 2),
+                        "restrict_err_arith": _sig(ka["restrict_taylor3"]["max_rel"], 2)}
+            if "interp_ms" in v:
+                m[label]["interp_t3_ms"] = v["interp_ms"]
+        h["mixed"] = m
+    if "small_u" in result:
+        h["small_u_latency_us"] = {k_: v["call_us"] for k_, v in result["small_u"].items()
+                                   if isinstance(v, dict)}
+    if "batched" in result:
+        b = result["batched"]
+        h["batched"] = {"faces": b["faces"], "f64_per_batch_ms": _sig(b["f64_per_batch_ms"]),
+                        "f64_plan_graph_ms": _sig(b["f64_plan_graph_ms"])}
+        for label in ("bf16x6", "f32"):
+            if label in b:
+                h["batched"][label] = {"graph_ms": _sig(b[label]["graph_ms"]),
+                                       "speedup_vs_f64_plan_graph": _sig(b[label]["speedup_vs_f64_plan_graph"], 3),
+                                       "err": _sig(b[label]["max_rel_err_vs_f64"], 2)}
+    if "mesh" in result:
+        me = result["mesh"]
+        h["mesh"] = {"faces": me["hanging_faces"], "f64_ms": _sig(me["f64_ms_per_step"]),
+                     "f64_plan_graph_ms": _sig(me["f64_plan_graph_ms_per_step"]),
+                     "mixed_graph_ms": _sig(me["mixed_graph_ms_per_step"]),
+                     "speedup_vs_f64_plan_graph": _sig(me["speedup_vs_f64_plan_graph"], 3),
+                     "err_e2e": _sig(me["mixed_max_rel_err_one_step"], 2),
+                     "err_arith": _sig(me["mixed_kernel_max_rel_err_one_step"], 2)}
+        if "f64_restrict_graph_ms_per_step" in me:
+            h["mesh"]["f64_restrict_mixed_graph_ms"] = _sig(me["f64_restrict_graph_ms_per_step"])
+            h["mesh"]["f64_restrict_speedup"] = _sig(me["f64_restrict_speedup_vs_f64_plan_graph"], 3)
+            h["mesh"]["f64_restrict_err_e2e"] = _sig(me["f64_restrict_max_rel_err_one_step"], 2)
+    if "mesh_patches" in result:
+        mp = result["mesh_patches"]
+        h["mesh_patches"] = {"f64_plan_graph_ms": _sig(mp["f64_plan_graph"]["ms_per_step"]),
+                             "bf16x6_plan_graph_ms": _sig(mp["bf16x6_plan_graph"]["ms_per_step"])}
+    if "patches" in result:
+        pa = result["patches"]
+        h["patches"] = {"unfused_ms": _sig(pa["unfused_ms_per_step"]), "fused_ms": _sig(pa["fused_ms_per_step"]),
+                        "bitwise_equal": pa["fused_equals_unfused_bitwise"]}
+    if "faces_2d" in result:
+        f2 = result["faces_2d"]
+        h["faces_2d"] = {"ms": _sig(f2["ms_per_step"]), "bf16x6_ms": _sig(f2["bf16x6"]["ms_per_step"])}
+    if "convergence" in result:
+        h["reports"] = ["convergence", "operator_build", "runtime_vs_p"]
+    h["detail"] = os.path.relpath(detail_path, ROOT) if detail_path else None
+    return h
+
+
+def write_detail(path, result):
+    """Write the full record of every leg; returns the path, or None."""
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(result, fh, indent=1)
+        return path
+    except OSError as exc:
+        progress(f"could not write {path}: {exc}")
+        return None
 
 
 def main():
@@ -690,6 +825,11 @@ def main():
         result["patches"] = patches_leg(args, torch, api, wl)
         progress("patch leg done")
 
+    if args.small_u_reps > 0:
+        result["small_u"] = small_u_leg(args, torch, api, wl)
+        progress("small-U leg done: " + json.dumps({k_: v["call_us"] for k_, v in result["small_u"].items()
+                                                     if isinstance(v, dict)}))
+
     if args.cpu_faces > 0:
         result["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_faces, n), torch)
         progress("cpu baseline done")
@@ -704,7 +844,8 @@ def main():
         result["runtime_vs_p"] = experiments.runtime_vs_p(device=dev)
         progress("reports done")
 
-    print(json.dumps(result), flush=True)
+    path = write_detail(args.detail, result)
+    print(json.dumps(headline(result, path), separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":
