@@ -107,11 +107,27 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _on_device(name, t):
+    """Every tensor handed to the library is a contiguous tensor on the
+    current GPU: kernels dereference raw pointers with dense strides."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must live on the GPU, not on {t.device}")
+    if t.device.index != torch.cuda.current_device():
+        raise TypeError(f"{name} lives on {t.device}, not on the current GPU "
+                        f"(cuda:{torch.cuda.current_device()})")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return t
+
+
 def _descriptors(orientation, subface, coarse_offset, fine_offset):
     for name, t, dt in (("orientation", orientation, torch.int8), ("subface", subface, torch.int8),
                         ("coarse_offset", coarse_offset, torch.int64), ("fine_offset", fine_offset, torch.int64)):
-        if t.dtype != dt or not t.is_contiguous():
-            raise TypeError(f"{name} must be a contiguous {dt} tensor")
+        if not isinstance(t, torch.Tensor) or t.dtype != dt:
+            raise TypeError(f"{name} must be a {dt} tensor")
+        _on_device(name, t)
     n = orientation.numel()
     if not (subface.numel() == coarse_offset.numel() == fine_offset.numel() == n):
         raise ValueError("descriptor arrays differ in length")
@@ -121,6 +137,8 @@ def _descriptors(orientation, subface, coarse_offset, fine_offset):
 def _mode(a, b, mode):
     """The C dtype code for tensors a, b: float64 -> FT_F64; float32 ->
     FT_F32 unless a split-bfloat16 mode is requested."""
+    _on_device("source buffer", a)
+    _on_device("destination buffer", b)
     if a.dtype != b.dtype or a.dtype not in _DTYPES:
         raise TypeError("coarse and fine must share dtype float64 or float32")
     if mode is None:
@@ -195,15 +213,27 @@ def restrict_patches(op, orientation, subface, coarse_offset, fine_offset, unkno
 def _copy_descriptors(sel, off_a, off_b):
     for name, t, dt in (("selector", sel, torch.int8), ("offset", off_a, torch.int64),
                         ("offset", off_b, torch.int64)):
-        if t.dtype != dt or not t.is_contiguous():
-            raise TypeError(f"{name} must be a contiguous {dt} tensor")
+        if not isinstance(t, torch.Tensor) or t.dtype != dt:
+            raise TypeError(f"{name} must be a {dt} tensor")
+        _on_device(name, t)
     n = sel.numel()
     if not (off_a.numel() == off_b.numel() == n):
         raise ValueError("descriptor arrays differ in length")
     return n
 
 
+def _counter(skipped):
+    """The optional int32 device counter of skipped items."""
+    if skipped is None:
+        return None
+    if not isinstance(skipped, torch.Tensor) or skipped.dtype != torch.int32 or skipped.numel() < 1:
+        raise TypeError("skipped must be an int32 tensor with at least one element")
+    return _on_device("skipped", skipped)
+
+
 def _elem_mode(*tensors):
+    for t in tensors:
+        _on_device("buffer", t)
     dts = {t.dtype for t in tensors}
     if len(dts) != 1 or tensors[0].dtype not in _DTYPES:
         raise TypeError("buffers must share dtype float64 or float32")
@@ -219,7 +249,7 @@ def gather_patch_faces(p, k, face, patch_offset, face_offset, halves, unknowns, 
         _lib.load().gather_patch_faces(
             p, k, n, _ptr(face), _ptr(patch_offset), _ptr(face_offset), halves, unknowns,
             _elem_mode(patches, faces), _ptr(patches), patches.numel(), _ptr(faces), faces.numel(),
-            _ptr(skipped), _stream_ptr(stream)),
+            _ptr(_counter(skipped)), _stream_ptr(stream)),
         "gather_patch_faces",
     )
 
@@ -233,7 +263,7 @@ def scatter_patch_faces(p, k, face, patch_offset, face_offset, halves, unknowns,
         _lib.load().scatter_patch_faces(
             p, k, n, _ptr(face), _ptr(patch_offset), _ptr(face_offset), halves, unknowns,
             _elem_mode(patches, faces), _ptr(faces), faces.numel(), _ptr(patches), patches.numel(),
-            _ptr(skipped), _stream_ptr(stream)),
+            _ptr(_counter(skipped)), _stream_ptr(stream)),
         "scatter_patch_faces",
     )
 
@@ -246,7 +276,7 @@ def copy_patch_halos(p, k, axis, lower_offset, upper_offset, unknowns, patches, 
     _check(
         _lib.load().copy_patch_halos(
             p, k, n, _ptr(axis), _ptr(lower_offset), _ptr(upper_offset), unknowns,
-            _elem_mode(patches), _ptr(patches), patches.numel(), _ptr(skipped),
+            _elem_mode(patches), _ptr(patches), patches.numel(), _ptr(_counter(skipped)),
             _stream_ptr(stream)),
         "copy_patch_halos",
     )

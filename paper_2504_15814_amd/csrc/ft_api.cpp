@@ -188,6 +188,21 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != op->device) return fail(FT_ERR_INVALID, "operator belongs to another device");
+  const int64_t esz = dtype == FT_F64 ? 8 : 4;
+  const struct {
+    const void* ptr;
+    int64_t bytes;
+    const char* what;
+  } ranges[6] = {{orientation, n_faces, "orientation"},
+                 {subface, n_faces, "subface"},
+                 {so, 8 * n_faces, "source offsets"},
+                 {dof, 8 * n_faces, "destination offsets"},
+                 {src, esz * src_elems, "source buffer"},
+                 {dst, esz * dst_elems, "destination buffer"}};
+  for (const auto& r : ranges) {
+    const std::string err = ft::device_range_error(r.ptr, r.bytes, dev, r.what);
+    if (!err.empty()) return fail(FT_ERR_INVALID, err);
+  }
   return FT_OK;
 }
 
@@ -195,7 +210,7 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
 // same-level halo exchange, which reads and writes one array.
 int check_copy(int p, int k, int64_t n, const void* sel, const void* off_a, const void* off_b,
                int halves, int unknowns, int dtype, const void* src, int64_t src_elems,
-               const void* dst, int64_t dst_elems) {
+               const void* dst, int64_t dst_elems, const void* skipped) {
   if (p < 1 || p > 1024) return fail(FT_ERR_UNSUPPORTED, "p must be in 1..1024");
   if (k < 1 || k > p) return fail(FT_ERR_UNSUPPORTED, "k must be in 1..p");
   const int64_t P = p + 2 * k;
@@ -209,6 +224,25 @@ int check_copy(int p, int k, int64_t n, const void* sel, const void* off_a, cons
   if (n == 0) return FT_OK;
   if (!sel || !off_a || !off_b || !src) return fail(FT_ERR_INVALID, "NULL descriptor or buffer");
   if (dst == src) return fail(FT_ERR_INVALID, "source and destination alias");
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const int64_t esz = dtype == FT_F64 ? 8 : 4;
+  const struct {
+    const void* ptr;
+    int64_t bytes;
+    const char* what;
+  } ranges[6] = {{sel, n, "face / axis selectors"},
+                 {off_a, 8 * n, "first offsets"},
+                 {off_b, 8 * n, "second offsets"},
+                 {src, esz * src_elems, "source buffer"},
+                 {dst ? dst : src, esz * dst_elems, "destination buffer"},
+                 {skipped, skipped ? 4 : 0, "skipped counter"}};
+  for (const auto& r : ranges) {
+    if (!r.ptr) continue;  // the optional counter
+    const std::string err = ft::device_range_error(r.ptr, r.bytes, dev, r.what);
+    if (!err.empty()) return fail(FT_ERR_INVALID, err);
+  }
   return FT_OK;
 }
 
@@ -276,6 +310,29 @@ void segment_entries(const ft_operator* op, int orientation, int subface,
 }  // namespace
 
 void ft::set_last_error(const std::string& msg) { g_last_error = msg; }
+
+std::string ft::device_range_error(const void* ptr, int64_t bytes, int dev, const char* what) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the lookup's error for the next launch check
+    return std::string(what) + " is not device memory";
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return std::string(what) + " is host memory, not device memory";
+  if (attr.device != dev) return std::string(what) + " lives on another device";
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return std::string(what) + ": allocation range lookup failed";
+  }
+  const uintptr_t lo = (uintptr_t)base, hi = lo + size, p = (uintptr_t)ptr;
+  if (bytes < 0 || p < lo || (uint64_t)bytes > (uint64_t)(hi - p))
+    return std::string(what) + " extends past the end of its device allocation";
+  return std::string();
+}
 
 extern "C" {
 
@@ -407,7 +464,7 @@ int gather_patch_faces(int p, int k, int64_t n, const int8_t* face, const int64_
                        const void* patches, int64_t patch_elems, void* faces, int64_t face_elems,
                        int* skipped, void* stream) {
   const int rc = check_copy(p, k, n, face, patch_offset, face_offset, halves, unknowns, dtype,
-                            patches, patch_elems, faces, face_elems);
+                            patches, patch_elems, faces, face_elems, skipped);
   if (rc != FT_OK || n == 0) return rc == FT_OK ? ok() : rc;
   ft::FaceCopyArgs c{ft::kGatherFaces, p, k, halves, n, face, patch_offset, face_offset,
                      unknowns, dtype == FT_F64 ? 8 : 4, patches, patch_elems, faces,
@@ -422,7 +479,7 @@ int scatter_patch_faces(int p, int k, int64_t n, const int8_t* face, const int64
                         const void* faces, int64_t face_elems, void* patches,
                         int64_t patch_elems, int* skipped, void* stream) {
   const int rc = check_copy(p, k, n, face, patch_offset, face_offset, halves, unknowns, dtype,
-                            faces, face_elems, patches, patch_elems);
+                            faces, face_elems, patches, patch_elems, skipped);
   if (rc != FT_OK || n == 0) return rc == FT_OK ? ok() : rc;
   ft::FaceCopyArgs c{ft::kScatterFaces, p, k, halves, n, face, patch_offset, face_offset,
                      unknowns, dtype == FT_F64 ? 8 : 4, faces, face_elems, patches,
@@ -436,7 +493,7 @@ int copy_patch_halos(int p, int k, int64_t n_pairs, const int8_t* axis,
                      const int64_t* lower_offset, const int64_t* upper_offset, int unknowns,
                      int dtype, void* patches, int64_t patch_elems, int* skipped, void* stream) {
   const int rc = check_copy(p, k, n_pairs, axis, lower_offset, upper_offset, FT_HALF_BOTH,
-                            unknowns, dtype, patches, patch_elems, nullptr, patch_elems);
+                            unknowns, dtype, patches, patch_elems, nullptr, patch_elems, skipped);
   if (rc != FT_OK || n_pairs == 0) return rc == FT_OK ? ok() : rc;
   ft::FaceCopyArgs c{ft::kHaloPairs, p, k, FT_HALF_BOTH, n_pairs, axis, lower_offset,
                      upper_offset, unknowns, dtype == FT_F64 ? 8 : 4, patches, patch_elems,

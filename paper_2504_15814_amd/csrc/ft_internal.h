@@ -213,6 +213,12 @@ namespace ft {
 // Message returned by transfer_last_error() on the calling thread.
 void set_last_error(const std::string& msg);
 
+// Empty if [ptr, ptr + bytes) lies inside one allocation of device memory of
+// device `dev`; otherwise a message naming `what`.  Host pointers (pageable or
+// pinned), other devices' memory and ranges running past the end of their
+// allocation are refused before any kernel can dereference them.
+std::string device_range_error(const void* ptr, int64_t bytes, int dev, const char* what);
+
 // Builder (host): fills blocks[] of op for op->direction/scheme/p/k.
 // Returns an empty string on success, else a message.
 std::string build_tables(ft_operator* op);

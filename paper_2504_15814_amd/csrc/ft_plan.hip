@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -177,6 +178,27 @@ __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restric
 
 }  // namespace ft
 
+namespace ft {
+// Device segment tables of a plan: for each phase, the segments in batch
+// order and in heavy-first order, uploaded once when the plan is built.  A
+// schedule change only picks the other table, so a captured graph keeps
+// valid kernel arguments; graphs share ownership of the tables, so they stay
+// valid after the plan is destroyed as well.
+struct PlanTables {
+  int device = -1;
+  PlanSeg* d_segs[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [phase][heavy first]
+  ~PlanTables() {
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (device >= 0) (void)hipSetDevice(device);
+    for (auto& ph : d_segs)
+      for (PlanSeg*& t : ph)
+        if (t) (void)hipFree(t);
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+}  // namespace ft
+
 struct ft_plan {
   std::vector<ft_plan_batch> batches;
   int U = 0, dtype = 0, flags = 0, device = -1, n_cu = 256;
@@ -184,7 +206,7 @@ struct ft_plan {
   void* fine = nullptr;
   int64_t coarse_elems = 0, fine_elems = 0;
   int64_t schedule = 0;
-  ft::PlanSeg* d_segs[2] = {nullptr, nullptr};
+  std::shared_ptr<ft::PlanTables> tables;
   int nseg[2] = {0, 0};
   int64_t total[2] = {0, 0};
   bool interp[2] = {false, false};  // the phase holds interpolation segments
@@ -195,6 +217,7 @@ struct ft_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int device = -1;
+  std::shared_ptr<ft::PlanTables> tables;  // read by the captured kernels
 };
 
 namespace {
@@ -230,19 +253,10 @@ double item_cost(const ft_operator* op) {
   return (double)op->R * w + 64.0 * op->R;  // FMAs + stores
 }
 
-void free_tables(ft_plan* plan) {
-  for (int ph = 0; ph < 2; ++ph) {
-    if (plan->d_segs[ph]) (void)hipFree(plan->d_segs[ph]);
-    plan->d_segs[ph] = nullptr;
-    plan->nseg[ph] = 0;
-    plan->total[ph] = 0;
-    plan->interp[ph] = false;
-  }
-}
-
-// (Re)build the device segment tables for the current schedule.
+// Build and upload the segment tables of both phases in both orders.
 int upload_tables(ft_plan* plan) {
-  free_tables(plan);
+  auto tables = std::make_shared<ft::PlanTables>();
+  tables->device = plan->device;
   const bool phased = plan->flags & FT_PLAN_RESTRICT_FIRST;
   for (int ph = 0; ph < 2; ++ph) {
     std::vector<int> idx;
@@ -252,40 +266,50 @@ int upload_tables(ft_plan* plan) {
       const int phase = phased ? (b.op->direction == FT_RESTRICT ? 0 : 1) : 0;
       if (phase == ph) idx.push_back(i);
     }
-    if (heavy_of(plan->schedule))
-      std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
-        return item_cost(plan->batches[a].op) > item_cost(plan->batches[c].op);
-      });
-    std::vector<ft::PlanSeg> segs;
-    int64_t item = 0;
-    for (int i : idx) {
-      const ft_plan_batch& b = plan->batches[i];
-      ft::PlanSeg sgm;
-      sgm.op = b.op->d_devop;
-      sgm.orientation = b.orientation;
-      sgm.subface = b.subface;
-      sgm.coarse_offset = b.coarse_offset;
-      sgm.fine_offset = b.fine_offset;
-      sgm.errors = b.op->d_errors;
-      sgm.anchors = b.op->E * b.op->E;
-      sgm.kind = plan_kind(b.op);
-      sgm.layout = (plan->flags & FT_PLAN_PATCHES) ? ft::kPatches : ft::kFaceBuffers;
-      sgm.item0 = item;
-      item += b.n_faces * sgm.anchors;
-      sgm.item_end = item;
-      segs.push_back(sgm);
-      if (b.op->direction == FT_INTERPOLATE) plan->interp[ph] = true;
+    plan->nseg[ph] = 0;
+    plan->total[ph] = 0;
+    plan->interp[ph] = false;
+    if (idx.empty()) continue;
+    for (int heavy = 0; heavy < 2; ++heavy) {
+      if (heavy)
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+          return item_cost(plan->batches[a].op) > item_cost(plan->batches[c].op);
+        });
+      std::vector<ft::PlanSeg> segs;
+      int64_t item = 0;
+      for (int i : idx) {
+        const ft_plan_batch& b = plan->batches[i];
+        ft::PlanSeg sgm;
+        sgm.op = b.op->d_devop;
+        sgm.orientation = b.orientation;
+        sgm.subface = b.subface;
+        sgm.coarse_offset = b.coarse_offset;
+        sgm.fine_offset = b.fine_offset;
+        sgm.errors = b.op->d_errors;
+        sgm.anchors = b.op->E * b.op->E;
+        sgm.kind = plan_kind(b.op);
+        sgm.layout = (plan->flags & FT_PLAN_PATCHES) ? ft::kPatches : ft::kFaceBuffers;
+        sgm.pad_ = 0;
+        sgm.item0 = item;
+        item += b.n_faces * sgm.anchors;
+        sgm.item_end = item;
+        segs.push_back(sgm);
+        if (b.op->direction == FT_INTERPOLATE) plan->interp[ph] = true;
+      }
+      ft::PlanSeg*& table = tables->d_segs[ph][heavy];
+      hipError_t e = hipMalloc(&table, segs.size() * sizeof(ft::PlanSeg));
+      if (e != hipSuccess) {
+        table = nullptr;
+        return e == hipErrorOutOfMemory ? pfail(FT_ERR_NOMEM, "plan table")
+                                        : phip(e, "hipMalloc plan table");
+      }
+      e = hipMemcpy(table, segs.data(), segs.size() * sizeof(ft::PlanSeg), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return phip(e, "uploading the plan table");
+      plan->nseg[ph] = (int)segs.size();
+      plan->total[ph] = item;
     }
-    if (segs.empty()) continue;
-    hipError_t e = hipMalloc(&plan->d_segs[ph], segs.size() * sizeof(ft::PlanSeg));
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? pfail(FT_ERR_NOMEM, "plan table")
-                                                         : phip(e, "hipMalloc plan table");
-    e = hipMemcpy(plan->d_segs[ph], segs.data(), segs.size() * sizeof(ft::PlanSeg),
-                  hipMemcpyHostToDevice);
-    if (e != hipSuccess) return phip(e, "uploading the plan table");
-    plan->nseg[ph] = (int)segs.size();
-    plan->total[ph] = item;
   }
+  plan->tables = std::move(tables);
   return FT_OK;
 }
 
@@ -296,14 +320,16 @@ hipError_t launch_phase(const ft_plan* plan, int ph, hipStream_t stream) {
   if (!persistent_of(plan->schedule)) {
     if (want > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((ft::plan_item_kernel<T, MODE>), dim3((unsigned)want), dim3(64 * wpb), 0,
-                       stream, plan->d_segs[ph], plan->nseg[ph], plan->total[ph], wpb,
+                       stream, plan->tables->d_segs[ph][heavy_of(plan->schedule)],
+                       plan->nseg[ph], plan->total[ph], wpb,
                        remap_of(plan->schedule), plan->U, static_cast<T*>(plan->coarse),
                        plan->coarse_elems, static_cast<T*>(plan->fine), plan->fine_elems);
     return hipGetLastError();
   }
   const int64_t blocks = std::min<int64_t>(want, (int64_t)plan->n_cu * bpc_of(plan->schedule));
   hipLaunchKernelGGL((ft::plan_kernel<T, MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0, stream,
-                     plan->d_segs[ph], plan->nseg[ph], wpb, remap_of(plan->schedule), plan->U,
+                     plan->tables->d_segs[ph][heavy_of(plan->schedule)], plan->nseg[ph], wpb,
+                     remap_of(plan->schedule), plan->U,
                      static_cast<T*>(plan->coarse), plan->coarse_elems,
                      static_cast<T*>(plan->fine), plan->fine_elems);
   return hipGetLastError();
@@ -369,6 +395,22 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
     if (dtype >= FT_F32_BF16X3 && b.op->direction == FT_INTERPOLATE && !b.op->d_wbf16)
       return pfail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
   }
+  // Every array the kernels will dereference must be device memory of this
+  // device, as large as stated.
+  const int64_t esz = dtype == FT_F64 ? 8 : 4;
+  std::string err = ft::device_range_error(coarse, esz * coarse_elems, dev, "coarse buffer");
+  if (err.empty()) err = ft::device_range_error(fine, esz * fine_elems, dev, "fine buffer");
+  for (int i = 0; i < n_batches && err.empty(); ++i) {
+    const ft_plan_batch& b = batches[i];
+    if (b.n_faces == 0) continue;
+    err = ft::device_range_error(b.orientation, b.n_faces, dev, "batch orientation");
+    if (err.empty()) err = ft::device_range_error(b.subface, b.n_faces, dev, "batch subface");
+    if (err.empty())
+      err = ft::device_range_error(b.coarse_offset, 8 * b.n_faces, dev, "batch coarse offsets");
+    if (err.empty())
+      err = ft::device_range_error(b.fine_offset, 8 * b.n_faces, dev, "batch fine offsets");
+  }
+  if (!err.empty()) return pfail(FT_ERR_INVALID, err);
   ft_plan* plan = new (std::nothrow) ft_plan();
   if (!plan) return pfail(FT_ERR_NOMEM, "host allocation failed");
   plan->batches.assign(batches, batches + n_batches);
@@ -386,8 +428,7 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
   plan->schedule = 4 | (1 << 8);  // 4 waves per block, one wave per work item
   const int rc = upload_tables(plan);
   if (rc != FT_OK) {
-    free_tables(plan);
-    delete plan;
+    delete plan;  // releases whatever tables were uploaded
     return rc;
   }
   *out = plan;
@@ -405,9 +446,7 @@ int run_transfer_plan(const ft_plan* plan, void* stream) {
 int transfer_plan_set_schedule(ft_plan* plan, int64_t schedule) {
   if (!plan) return pfail(FT_ERR_INVALID, "plan is NULL");
   if (!valid_schedule(schedule)) return pfail(FT_ERR_INVALID, "invalid schedule");
-  const bool reorder = heavy_of(schedule) != heavy_of(plan->schedule);
-  plan->schedule = schedule;
-  if (reorder) return upload_tables(plan);
+  plan->schedule = schedule;  // both segment orders are uploaded already
   return FT_OK;
 }
 
@@ -479,12 +518,7 @@ int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_
 
 int destroy_transfer_plan(ft_plan* plan) {
   if (!plan) return FT_OK;
-  int prev = -1;
-  (void)hipGetDevice(&prev);
-  (void)hipSetDevice(plan->device);
-  free_tables(plan);
-  if (prev >= 0) (void)hipSetDevice(prev);
-  delete plan;
+  delete plan;  // the tables go with the last graph that still uses them
   return FT_OK;
 }
 
@@ -495,6 +529,7 @@ int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out) {
   ft_graph* g = new (std::nothrow) ft_graph();
   if (!g) return pfail(FT_ERR_NOMEM, "host allocation failed");
   g->device = plan->device;
+  g->tables = plan->tables;
   hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete g;

@@ -110,3 +110,117 @@ def abs_weighted_sums(direction, scheme, batch, src, dst_len, faces=None):
         y = out[int(do[f]): int(do[f]) + ncell * U].reshape(ncell, U)
         y[rows] = np.abs(W) @ x
     return out
+
+
+# ---------------------------------------------------------------------------
+# Full-size checks: every face on the device, a sample against the oracle
+# ---------------------------------------------------------------------------
+def local_written(direction, scheme, p, k, U, o, s, dim=3):
+    """Element indices, relative to a face's destination offset, that one
+    face of orientation o and subface s writes (the oracle's operator rows)."""
+    if dim == 3:
+        rows, _ = oracle.transfer_operator(direction, scheme, p, k, int(o), int(s))
+    else:
+        rows, _ = oracle.transfer2d.transfer_operator(direction, scheme, p, k, int(o), int(s))
+    return (np.asarray(rows)[:, None] * U + np.arange(U)[None, :]).ravel()
+
+
+def device_written_mask(direction, scheme, p, k, U, orientation, subface, dst_offset, dst_len,
+                        device, dim=3, chunk=2048):
+    """Boolean device tensor over the destination array: True where some face
+    of the batch writes.  Built per (orientation, subface) group from the
+    oracle's rows, in chunks of faces."""
+    o = orientation.cpu().numpy().astype(np.int64)
+    s = subface.cpu().numpy().astype(np.int64)
+    offs = dst_offset.to(device)
+    mask = torch.zeros(dst_len, dtype=torch.bool, device=device)
+    key = o * 16 + s
+    for kv in np.unique(key):
+        faces = torch.from_numpy(np.flatnonzero(key == kv)).to(device)
+        loc = torch.from_numpy(local_written(direction, scheme, p, k, U, kv // 16, kv % 16, dim)).to(device)
+        for c0 in range(0, faces.numel(), chunk):
+            idx = offs[faces[c0:c0 + chunk]][:, None] + loc[None, :]
+            mask[idx.reshape(-1)] = True
+    return mask
+
+
+def _bits(t):
+    return t.view(torch.int64) if t.dtype == torch.float64 else t.view(torch.int32)
+
+
+def check_written_region(dst, before, mask, chunk=1 << 28):
+    """On the device, over the whole destination: every element in `mask`
+    differs from `before` (a sentinel fill, so every written element was
+    written) and every element outside it is bit-identical to `before`."""
+    d, b = _bits(dst), _bits(before)
+    for c0 in range(0, d.numel(), chunk):
+        dd, bb, mm = d[c0:c0 + chunk], b[c0:c0 + chunk], mask[c0:c0 + chunk]
+        same = dd == bb
+        assert not bool((same & mm).any()), "an element of a written half kept its sentinel"
+        assert not bool((~same & ~mm).any()), "an element outside the written halves changed"
+
+
+def compact_faces(t, offsets, faces, elems):
+    """Host float64 copy of `elems` elements at offsets[f] for the sampled
+    faces, back to back (face i at i * elems)."""
+    offs = offsets.cpu().numpy()
+    return np.concatenate([t[int(offs[f]):int(offs[f]) + elems].double().cpu().numpy() for f in faces])
+
+
+def compact_batch(batch, faces, coarse=None, fine=None):
+    """A host FaceBatch holding the sampled faces' coarse and fine buffers
+    (or the given tensors instead), each face at i * face_elems."""
+    from paper_2504_15814_amd import workloads as wl
+
+    E = batch.face_elems
+    offs = torch.arange(len(faces), dtype=torch.int64) * E
+    c = compact_faces(batch.coarse if coarse is None else coarse, batch.coarse_offset, faces, E)
+    f = compact_faces(batch.fine if fine is None else fine, batch.fine_offset, faces, E)
+    sel = torch.from_numpy(np.asarray(faces, dtype=np.int64))
+    return wl.FaceBatch(batch.p, batch.k, batch.U, batch.orientation.cpu()[sel].contiguous(),
+                        batch.subface.cpu()[sel].contiguous(), offs, offs.clone(),
+                        torch.from_numpy(c), torch.from_numpy(f))
+
+
+def run_gpu_device(direction, scheme, batch, dtype=torch.float64, op=None, mode=None):
+    """Apply the HIP path into a sentinel-filled destination; returns
+    (destination, source, sentinel copy) as device tensors."""
+    coarse = batch.coarse.to(dtype)
+    fine = batch.fine.to(dtype)
+    if op is None:
+        op = api.build_transfer_operator(direction, scheme, batch.p, batch.k)
+    src = coarse if direction == 0 else fine
+    dst = torch.full_like(fine if direction == 0 else coarse, SENTINEL)
+    if direction == 0:
+        api.interpolate_faces(op, batch.orientation, batch.subface, batch.coarse_offset,
+                              batch.fine_offset, batch.U, coarse, dst, mode=mode)
+    else:
+        api.restrict_faces(op, batch.orientation, batch.subface, batch.coarse_offset,
+                           batch.fine_offset, batch.U, fine, dst, mode=mode)
+    torch.cuda.synchronize(dst.device)
+    assert op.errors() == 0
+    return dst, src, torch.full_like(dst, SENTINEL)
+
+
+def check_full_size(direction, scheme, batch, dst, before, faces, tol=1e-12, src=None):
+    """Whole-batch region check on the device plus an oracle comparison of
+    the sampled faces (their buffers copied out compactly)."""
+    dst_off = batch.fine_offset if direction == 0 else batch.coarse_offset
+    mask = device_written_mask(direction, scheme, batch.p, batch.k, batch.U, batch.orientation,
+                               batch.subface, dst_off, dst.numel(), dst.device)
+    check_written_region(dst, before, mask)
+    del mask
+    if direction == 0:
+        cb = compact_batch(batch, faces, coarse=src)
+    else:
+        cb = compact_batch(batch, faces, fine=src)
+    got = compact_faces(dst, dst_off, faces, batch.face_elems)
+    src_np = (cb.coarse if direction == 0 else cb.fine).numpy()
+    before_np = compact_faces(before, dst_off, faces, batch.face_elems)
+    want, (o, s, doff) = run_oracle(direction, scheme, cb, src_np, before_np)
+    m, copy = written_mask(direction, scheme, cb.p, cb.k, cb.U, o, s, doff, len(got))
+    assert np.array_equal(got[~m], before_np[~m])
+    emax, erms = rel_errors(got, want, m, cb.U)
+    assert emax.max() <= tol, (emax.max(), erms.max())
+    assert np.array_equal(got[copy], want[copy])
+    return emax

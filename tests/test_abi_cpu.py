@@ -297,3 +297,24 @@ def test_general_p_anchor_counts():
     for p, ei, er in ((6, 2, 2), (9, 3, 3), (7, 3, 3), (8, 4, 3), (10, 4, 4), (11, 5, 4)):
         assert api.build_transfer_operator(0, 2, p, 2, api.FT_BUILD_HOST_ONLY).info()["anchors"] == ei * ei
         assert api.build_transfer_operator(1, 2, p, 2, api.FT_BUILD_HOST_ONLY).info()["anchors"] == er * er
+
+
+def test_binding_rejects_host_tensors_before_any_call():
+    """The binding hands the library only contiguous tensors on the current
+    GPU: host tensors are refused in Python, before the C ABI is reached."""
+    import torch
+
+    op = api.build_transfer_operator(0, 2, 9, 3, api.FT_BUILD_HOST_ONLY)
+    o = torch.zeros(2, dtype=torch.int8)
+    off = torch.zeros(2, dtype=torch.int64)
+    buf = torch.zeros(2 * 6 * 81 * 3, dtype=torch.float64)
+    for fn in (api.interpolate_faces, api.restrict_faces, api.interpolate_patches, api.restrict_patches):
+        with pytest.raises(TypeError, match="GPU"):
+            fn(op, o, o, off, off, 3, buf, buf.clone())
+    with pytest.raises(TypeError, match="GPU"):
+        api.gather_patch_faces(9, 3, o, off, off, api.FT_HALF_BOTH, 3, buf, buf.clone())
+    with pytest.raises(TypeError):
+        api.interpolate_faces(op, o.numpy(), o, off, off, 3, buf, buf.clone())
+    with pytest.raises(TypeError):
+        api.gather_patch_faces(9, 3, o, off, off, api.FT_HALF_BOTH, 3, buf, buf.clone(),
+                               skipped=torch.zeros(1, dtype=torch.int64))

@@ -129,6 +129,31 @@ def test_full_size_mesh_step(mesh_full):
     assert rop.errors() == 0 and iop.errors() == 0
     del pc, pf
 
+    # Every face on the device, one direction at a time: restriction into the
+    # shared coarse faces (whose written segments start as sentinels) and
+    # interpolation into the fine halos (likewise) write every element of
+    # their regions and nothing else.
+    d = (mf.orientation, mf.subface, mf.coarse_offset, mf.fine_offset)
+    dev = mf.coarse.device
+    cmask = gh.device_written_mask(1, 3, mf.p, mf.k, U, mf.orientation, mf.subface, mf.coarse_offset,
+                                   mf.coarse.numel(), dev)
+    cs = mf.coarse.clone()
+    cs[cmask] = gh.SENTINEL
+    cb = cs.clone()
+    api.restrict_faces(rop, *d, U, mf.fine, cs)
+    torch.cuda.synchronize()
+    gh.check_written_region(cs, cb, cmask)
+    del cmask, cs, cb
+    fmask = gh.device_written_mask(0, 3, mf.p, mf.k, U, mf.orientation, mf.subface, mf.fine_offset,
+                                   mf.fine.numel(), dev)
+    fs = mf.fine.clone()
+    fs[fmask] = gh.SENTINEL
+    fb = fs.clone()
+    api.interpolate_faces(iop, *d, U, mf.coarse, fs)
+    torch.cuda.synchronize()
+    gh.check_written_region(fs, fb, fmask)
+    del fmask, fs, fb
+
     # oracle on compact copies of 12 coarse faces and their nine fine faces
     o, s = mf.orientation.cpu().numpy(), mf.subface.cpu().numpy()
     co, fo = mf.coarse_offset.cpu().numpy(), mf.fine_offset.cpu().numpy()

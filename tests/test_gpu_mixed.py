@@ -125,9 +125,30 @@ def w3_full(dev):
 @pytest.mark.parametrize("mode", MODES)
 def test_full_size_precision_workload_sampled(w3_full, mode):
     """20,000 faces x 59 unknowns (scaled 1e-6 .. 1e3), third order, in the
-    benchmark's launch configuration; a seeded sample of 150 faces is
-    recomputed by the oracle on the same float32 inputs."""
+    benchmark's launch configuration.  On the device, for all faces: every
+    written element was written and nothing else changed.  A seeded sample of
+    150 faces is recomputed by the oracle on the same float32 inputs."""
     rng = np.random.default_rng(300 + mode)
     faces = np.sort(rng.choice(w3_full.n, size=150, replace=False))
-    emax, _ = check_mode(w3_full, 3, mode, faces=faces)
+    b = w3_full
+    dst, src, before = gh.run_gpu_device(0, 3, b, torch.float32, mode=mode)
+    mask = gh.device_written_mask(0, 3, b.p, b.k, b.U, b.orientation, b.subface, b.fine_offset,
+                                  dst.numel(), dst.device)
+    gh.check_written_region(dst, before, mask)
+    del mask
+    # the sample, on compact host copies of its faces
+    cb = gh.compact_batch(b, faces, coarse=src)
+    got = gh.compact_faces(dst, b.fine_offset, faces, b.face_elems)
+    before_np = gh.compact_faces(before, b.fine_offset, faces, b.face_elems)
+    del dst, src, before
+    src_np = cb.coarse.numpy()
+    want, (o, s, doff) = gh.run_oracle(0, 3, cb, src_np, before_np)
+    m, copy = gh.written_mask(0, 3, cb.p, cb.k, cb.U, o, s, doff, len(got))
+    scale = gh.abs_weighted_sums(0, 3, cb, src_np, len(got))
+    err = np.abs(got - want)
+    bound = C[mode] * scale + 2.0**-24 * np.abs(want)
+    assert np.all(err[m] <= bound[m]), float(np.max(err[m] / np.maximum(bound[m], 1e-300)))
+    assert np.array_equal(got[copy], want[copy])
+    assert np.array_equal(got[~m], before_np[~m])
+    emax, _ = gh.rel_errors(got, want, m, cb.U)
     assert emax.max() < EMAX[mode]

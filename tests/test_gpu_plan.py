@@ -254,12 +254,37 @@ def test_full_size_uneven_mix_sampled(dev):
     plan.run()
     torch.cuda.synchronize()
     assert torch.equal(pc, rc) and torch.equal(pf, rf)
+    del rc, rf
+    # All 50,000 faces on the device: the halves the plan writes (fine ghost
+    # halves of interpolated faces, coarse segments of restricted faces) are
+    # never read by the launch, so they start as sentinels; afterwards each
+    # of their elements was written and nothing else changed.
+    U = mb.U
+    fmask = torch.zeros(mb.fine.numel(), dtype=torch.bool, device=dev)
+    cmask = torch.zeros(mb.coarse.numel(), dtype=torch.bool, device=dev)
+    for (d, sch, p, k), idx in mb.groups().items():
+        o, s_, co_, fo_ = mb.subset(idx)
+        if d == 0:
+            fmask |= gh.device_written_mask(0, sch, p, k, U, o, s_, fo_, fmask.numel(), dev)
+        else:
+            cmask |= gh.device_written_mask(1, sch, p, k, U, o, s_, co_, cmask.numel(), dev)
+    fs, cs = mb.fine.clone(), mb.coarse.clone()
+    fs[fmask] = gh.SENTINEL
+    cs[cmask] = gh.SENTINEL
+    fb, cb = fs.clone(), cs.clone()
+    plan2 = api.build_transfer_plan(batches_of(mb, ops), U, cs, fs, mode=api.FT_F32_BF16X6)
+    plan2.schedule = plan.schedule
+    plan2.run()
+    torch.cuda.synchronize()
+    assert torch.equal(cs, pc) and torch.equal(fs, pf)
+    gh.check_written_region(fs, fb, fmask)
+    gh.check_written_region(cs, cb, cmask)
+    del fmask, cmask, fs, cs, fb, cb, plan2
     coarse_in = mb.coarse.double().cpu().numpy()
     fine_in = mb.fine.double().cpu().numpy()
     pc_np, pf_np = pc.double().cpu().numpy(), pf.double().cpu().numpy()
     co, fo = mb.coarse_offset.cpu().numpy(), mb.fine_offset.cpu().numpy()
     orient, sub = mb.orientation.cpu().numpy(), mb.subface.cpu().numpy()
-    U = mb.U
     for (d, sch, p, k), idx in mb.groups().items():
         for f in idx[:2].tolist():
             rows, W = oracle.transfer_operator(d, sch, p, k, int(orient[f]), int(sub[f]))
