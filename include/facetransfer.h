@@ -354,6 +354,27 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
  * synchronisation: capturable). */
 int run_transfer_plan(const ft_plan* plan, void* stream);
 
+/* One fused launch over `n_batches` batches, as build_transfer_plan +
+ * run_transfer_plan with the default schedule would run them, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): this call allocates
+ * nothing.  The batches' segment table goes into a fixed workspace of the
+ * library in device memory (one per device, held until the process ends,
+ * room for 128 non-empty batches per phase, 20 KiB), written by a small
+ * kernel on `stream` before the transfer kernels.  Arguments, checks and
+ * results are those of build_transfer_plan / run_transfer_plan (bitwise
+ * equal to the plan's outputs); nothing needs to be zero beforehand.
+ * Asynchronous on `stream`.  Calls on one device share the workspace: calls
+ * that overlap in time (on different streams, without ordering between
+ * them) race and must not be issued; calls on one stream are safe.
+ * Errors: as build_transfer_plan, plus FT_ERR_UNSUPPORTED for more than 128
+ * non-empty batches in one phase (FT_PLAN_RESTRICT_FIRST puts restriction
+ * batches in phase 0 and interpolation batches in phase 1; otherwise every
+ * batch is in phase 0). */
+int run_transfer_batches(const ft_plan_batch* batches, int n_batches, int unknowns, int dtype,
+                         void* coarse, int64_t coarse_elems, void* fine, int64_t fine_elems,
+                         int flags, void* stream);
+
 /* Schedule of a plan, packed as waves_per_block | blocks_per_cu << 8 |
  * xcd_remap << 16 | heavy_first << 17 | persistent << 18 (waves_per_block
  * in {1, 2, 4}, blocks_per_cu in 1..64).  persistent = 1: a grid of

@@ -83,6 +83,11 @@ SIGNATURES = {
          c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(c_void_p)],
     ),
     "run_transfer_plan": (ctypes.c_int, [c_void_p, c_void_p]),
+    "run_transfer_batches": (
+        ctypes.c_int,
+        [ctypes.POINTER(PlanBatch), ctypes.c_int, ctypes.c_int, ctypes.c_int, c_void_p, ctypes.c_int64,
+         c_void_p, ctypes.c_int64, ctypes.c_int, c_void_p],
+    ),
     "transfer_plan_set_schedule": (ctypes.c_int, [c_void_p, ctypes.c_int64]),
     "transfer_plan_get_schedule": (ctypes.c_int, [c_void_p, c_int64_p]),
     "transfer_plan_autotune": (

@@ -373,19 +373,36 @@ class TransferGraph:
             pass
 
 
-def build_transfer_plan(batches, unknowns, coarse, fine, mode=None, flags=0):
-    dt = _mode(coarse, fine, mode)
+def _plan_batches(batches):
     arr = (_lib.PlanBatch * len(batches))()
-    keep = [coarse, fine]
+    keep = []
     for i, (op, o, s, co, fo) in enumerate(batches):
         n = _descriptors(o, s, co, fo)
         arr[i] = _lib.PlanBatch(op.handle, n, o.data_ptr(), s.data_ptr(), co.data_ptr(), fo.data_ptr())
         keep.extend([op, o, s, co, fo])
+    return arr, keep
+
+
+def build_transfer_plan(batches, unknowns, coarse, fine, mode=None, flags=0):
+    dt = _mode(coarse, fine, mode)
+    arr, keep = _plan_batches(batches)
+    keep.extend([coarse, fine])
     h = ctypes.c_void_p()
     _check(_lib.load().build_transfer_plan(arr, len(batches), unknowns, dt, _ptr(coarse), coarse.numel(),
                                            _ptr(fine), fine.numel(), flags, ctypes.byref(h)),
            "build_transfer_plan")
     return TransferPlan(h.value, keep)
+
+
+def run_transfer_batches(batches, unknowns, coarse, fine, mode=None, flags=0, stream=None):
+    """One fused launch over the batches without a plan object; the library
+    allocates nothing (its segment table sits in a fixed device workspace).
+    Calls on one GPU that overlap in time race on that workspace."""
+    dt = _mode(coarse, fine, mode)
+    arr, _ = _plan_batches(batches)
+    _check(_lib.load().run_transfer_batches(arr, len(batches), unknowns, dt, _ptr(coarse), coarse.numel(),
+                                            _ptr(fine), fine.numel(), flags, _stream_ptr(stream)),
+           "run_transfer_batches")
 
 
 def run_transfer_plan(plan, stream=None):

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -176,9 +177,28 @@ __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restric
   }
 }
 
-}  // namespace ft
+// ---------------------------------------------------------------------------
+// Allocation-free fused launch (run_transfer_batches): the segment tables of
+// one call live in `scratch`, a fixed array of this library in device memory
+// (every device holds its own copy), filled by a small kernel whose
+// arguments carry the segments, then read by plan_item_kernel.
+// ---------------------------------------------------------------------------
+constexpr int kScratchSegs = 128;  // segments per phase
+static __device__ __align__(256) PlanSeg scratch[2 * kScratchSegs];
 
-namespace ft {
+constexpr int kFillSegs = 16;  // segments per fill launch (passed by value)
+struct SegFill {
+  PlanSeg seg[kFillSegs];
+  int first;  // first table entry written
+  int count;
+};
+
+__global__ __launch_bounds__(64) void fill_segments_kernel(PlanSeg* __restrict__ table,
+                                                           const SegFill fill) {
+  const int i = threadIdx.x;
+  if (i < fill.count) table[fill.first + i] = fill.seg[i];
+}
+
 // Device segment tables of a plan: for each phase, the segments in batch
 // order and in heavy-first order, uploaded once when the plan is built.  A
 // schedule change only picks the other table, so a captured graph keeps
@@ -253,18 +273,90 @@ double item_cost(const ft_operator* op) {
   return (double)op->R * w + 64.0 * op->R;  // FMAs + stores
 }
 
+// Host checks shared by plans and run_transfer_batches; on success *dev_out
+// is the current device.
+int check_batches(const ft_plan_batch* batches, int n_batches, int unknowns, int dtype,
+                  const void* coarse, int64_t coarse_elems, const void* fine, int64_t fine_elems,
+                  int flags, int* dev_out) {
+  if (!batches || n_batches < 1) return pfail(FT_ERR_INVALID, "need at least one batch");
+  if (unknowns < 1 || unknowns > 4096) return pfail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
+  if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return pfail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (flags & ~(FT_PLAN_RESTRICT_FIRST | FT_PLAN_PATCHES))
+    return pfail(FT_ERR_INVALID, "unknown flags");
+  // Face buffers: one array for coarse and fine would let a face overwrite
+  // what it reads.  Patches: reads are face views, writes halos of other
+  // faces, so one pool may hold both.
+  if (!coarse || !fine || coarse_elems < 0 || fine_elems < 0 ||
+      (coarse == fine && !(flags & FT_PLAN_PATCHES)))
+    return pfail(FT_ERR_INVALID, "bad coarse / fine buffers");
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return phip(e, "hipGetDevice");
+  for (int i = 0; i < n_batches; ++i) {
+    const ft_plan_batch& b = batches[i];
+    if (!b.op || b.n_faces < 0) return pfail(FT_ERR_INVALID, "batch with NULL op or n_faces < 0");
+    if (!b.op->on_device || b.op->device != dev)
+      return pfail(FT_ERR_INVALID, "batch operator is host-only or on another device");
+    if (b.op->dim != 3) return pfail(FT_ERR_UNSUPPORTED, "plans take three-dimensional operators");
+    if (b.n_faces > 0 && (!b.orientation || !b.subface || !b.coarse_offset || !b.fine_offset))
+      return pfail(FT_ERR_INVALID, "batch with NULL descriptor arrays");
+    if (b.n_faces * (int64_t)b.op->E * b.op->E >= ((int64_t)1 << 31))
+      return pfail(FT_ERR_UNSUPPORTED, "batch too large (faces x anchors must stay below 2^31)");
+    if (dtype >= FT_F32_BF16X3 && b.op->direction == FT_INTERPOLATE && !b.op->d_wbf16)
+      return pfail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
+  }
+  // Every array the kernels will dereference must be device memory of this
+  // device, as large as stated.
+  const int64_t esz = dtype == FT_F64 ? 8 : 4;
+  std::string err = ft::device_range_error(coarse, esz * coarse_elems, dev, "coarse buffer");
+  if (err.empty()) err = ft::device_range_error(fine, esz * fine_elems, dev, "fine buffer");
+  for (int i = 0; i < n_batches && err.empty(); ++i) {
+    const ft_plan_batch& b = batches[i];
+    if (b.n_faces == 0) continue;
+    err = ft::device_range_error(b.orientation, b.n_faces, dev, "batch orientation");
+    if (err.empty()) err = ft::device_range_error(b.subface, b.n_faces, dev, "batch subface");
+    if (err.empty())
+      err = ft::device_range_error(b.coarse_offset, 8 * b.n_faces, dev, "batch coarse offsets");
+    if (err.empty())
+      err = ft::device_range_error(b.fine_offset, 8 * b.n_faces, dev, "batch fine offsets");
+  }
+  if (!err.empty()) return pfail(FT_ERR_INVALID, err);
+  *dev_out = dev;
+  return FT_OK;
+}
+
+// Phase of a batch: restriction first with FT_PLAN_RESTRICT_FIRST.
+int phase_of(const ft_plan_batch& b, int flags) {
+  return (flags & FT_PLAN_RESTRICT_FIRST) ? (b.op->direction == FT_RESTRICT ? 0 : 1) : 0;
+}
+
+// Segment of one batch whose work items start at item0.
+ft::PlanSeg make_segment(const ft_plan_batch& b, int flags, int64_t item0) {
+  ft::PlanSeg sgm;
+  sgm.op = b.op->d_devop;
+  sgm.orientation = b.orientation;
+  sgm.subface = b.subface;
+  sgm.coarse_offset = b.coarse_offset;
+  sgm.fine_offset = b.fine_offset;
+  sgm.errors = b.op->d_errors;
+  sgm.anchors = b.op->E * b.op->E;
+  sgm.kind = plan_kind(b.op);
+  sgm.layout = (flags & FT_PLAN_PATCHES) ? ft::kPatches : ft::kFaceBuffers;
+  sgm.pad_ = 0;
+  sgm.item0 = item0;
+  sgm.item_end = item0 + b.n_faces * sgm.anchors;
+  return sgm;
+}
+
 // Build and upload the segment tables of both phases in both orders.
 int upload_tables(ft_plan* plan) {
   auto tables = std::make_shared<ft::PlanTables>();
   tables->device = plan->device;
-  const bool phased = plan->flags & FT_PLAN_RESTRICT_FIRST;
   for (int ph = 0; ph < 2; ++ph) {
     std::vector<int> idx;
     for (int i = 0; i < (int)plan->batches.size(); ++i) {
       const ft_plan_batch& b = plan->batches[i];
-      if (b.n_faces == 0) continue;
-      const int phase = phased ? (b.op->direction == FT_RESTRICT ? 0 : 1) : 0;
-      if (phase == ph) idx.push_back(i);
+      if (b.n_faces > 0 && phase_of(b, plan->flags) == ph) idx.push_back(i);
     }
     plan->nseg[ph] = 0;
     plan->total[ph] = 0;
@@ -279,21 +371,8 @@ int upload_tables(ft_plan* plan) {
       int64_t item = 0;
       for (int i : idx) {
         const ft_plan_batch& b = plan->batches[i];
-        ft::PlanSeg sgm;
-        sgm.op = b.op->d_devop;
-        sgm.orientation = b.orientation;
-        sgm.subface = b.subface;
-        sgm.coarse_offset = b.coarse_offset;
-        sgm.fine_offset = b.fine_offset;
-        sgm.errors = b.op->d_errors;
-        sgm.anchors = b.op->E * b.op->E;
-        sgm.kind = plan_kind(b.op);
-        sgm.layout = (plan->flags & FT_PLAN_PATCHES) ? ft::kPatches : ft::kFaceBuffers;
-        sgm.pad_ = 0;
-        sgm.item0 = item;
-        item += b.n_faces * sgm.anchors;
-        sgm.item_end = item;
-        segs.push_back(sgm);
+        segs.push_back(make_segment(b, plan->flags, item));
+        item = segs.back().item_end;
         if (b.op->direction == FT_INTERPOLATE) plan->interp[ph] = true;
       }
       ft::PlanSeg*& table = tables->d_segs[ph][heavy];
@@ -354,6 +433,40 @@ int run_plan(const ft_plan* plan, hipStream_t stream) {
   return FT_OK;
 }
 
+// Device address of `scratch` on device `dev` (the current device), looked
+// up once per device and kept: host code never passes the array's own name.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+ft::PlanSeg* g_scratch[kMaxDevices] = {};
+
+int scratch_on(int dev, ft::PlanSeg** out) {
+  if (dev < 0 || dev >= kMaxDevices) return pfail(FT_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(ft::scratch));
+    if (e != hipSuccess) return phip(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return pfail(FT_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch[dev] = static_cast<ft::PlanSeg*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return FT_OK;
+}
+
+// One wave per work item, four waves per block, over `nseg` segments at
+// `segs` (the default plan schedule).
+template <typename T, int MODE>
+hipError_t launch_items(const ft::PlanSeg* segs, int nseg, int64_t total, int U, void* coarse,
+                        int64_t coarse_elems, void* fine, int64_t fine_elems, hipStream_t stream) {
+  constexpr int wpb = 4;
+  const int64_t blocks = (total + wpb - 1) / wpb;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((ft::plan_item_kernel<T, MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0,
+                     stream, segs, nseg, total, wpb, 0, U, static_cast<T*>(coarse), coarse_elems,
+                     static_cast<T*>(fine), fine_elems);
+  return hipGetLastError();
+}
+
 bool valid_schedule(int64_t s) {
   const int w = wpb_of(s), b = bpc_of(s);
   return (w == 1 || w == 2 || w == 4) && b >= 1 && b <= 64 && (s >> 19) == 0;
@@ -368,49 +481,10 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
                         int flags, ft_plan** out) {
   if (!out) return pfail(FT_ERR_INVALID, "out is NULL");
   *out = nullptr;
-  if (!batches || n_batches < 1) return pfail(FT_ERR_INVALID, "need at least one batch");
-  if (unknowns < 1 || unknowns > 4096) return pfail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
-  if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return pfail(FT_ERR_UNSUPPORTED, "unsupported dtype");
-  if (flags & ~(FT_PLAN_RESTRICT_FIRST | FT_PLAN_PATCHES))
-    return pfail(FT_ERR_INVALID, "unknown flags");
-  // Face buffers: one array for coarse and fine would let a face overwrite
-  // what it reads.  Patches: reads are face views, writes halos of other
-  // faces, so one pool may hold both.
-  if (!coarse || !fine || coarse_elems < 0 || fine_elems < 0 ||
-      (coarse == fine && !(flags & FT_PLAN_PATCHES)))
-    return pfail(FT_ERR_INVALID, "bad coarse / fine buffers");
   int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return phip(e, "hipGetDevice");
-  for (int i = 0; i < n_batches; ++i) {
-    const ft_plan_batch& b = batches[i];
-    if (!b.op || b.n_faces < 0) return pfail(FT_ERR_INVALID, "batch with NULL op or n_faces < 0");
-    if (!b.op->on_device || b.op->device != dev)
-      return pfail(FT_ERR_INVALID, "batch operator is host-only or on another device");
-    if (b.op->dim != 3) return pfail(FT_ERR_UNSUPPORTED, "plans take three-dimensional operators");
-    if (b.n_faces > 0 && (!b.orientation || !b.subface || !b.coarse_offset || !b.fine_offset))
-      return pfail(FT_ERR_INVALID, "batch with NULL descriptor arrays");
-    if (b.n_faces * (int64_t)b.op->E * b.op->E >= ((int64_t)1 << 31))
-      return pfail(FT_ERR_UNSUPPORTED, "batch too large (faces x anchors must stay below 2^31)");
-    if (dtype >= FT_F32_BF16X3 && b.op->direction == FT_INTERPOLATE && !b.op->d_wbf16)
-      return pfail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
-  }
-  // Every array the kernels will dereference must be device memory of this
-  // device, as large as stated.
-  const int64_t esz = dtype == FT_F64 ? 8 : 4;
-  std::string err = ft::device_range_error(coarse, esz * coarse_elems, dev, "coarse buffer");
-  if (err.empty()) err = ft::device_range_error(fine, esz * fine_elems, dev, "fine buffer");
-  for (int i = 0; i < n_batches && err.empty(); ++i) {
-    const ft_plan_batch& b = batches[i];
-    if (b.n_faces == 0) continue;
-    err = ft::device_range_error(b.orientation, b.n_faces, dev, "batch orientation");
-    if (err.empty()) err = ft::device_range_error(b.subface, b.n_faces, dev, "batch subface");
-    if (err.empty())
-      err = ft::device_range_error(b.coarse_offset, 8 * b.n_faces, dev, "batch coarse offsets");
-    if (err.empty())
-      err = ft::device_range_error(b.fine_offset, 8 * b.n_faces, dev, "batch fine offsets");
-  }
-  if (!err.empty()) return pfail(FT_ERR_INVALID, err);
+  const int rc0 = check_batches(batches, n_batches, unknowns, dtype, coarse, coarse_elems, fine,
+                                fine_elems, flags, &dev);
+  if (rc0 != FT_OK) return rc0;
   ft_plan* plan = new (std::nothrow) ft_plan();
   if (!plan) return pfail(FT_ERR_NOMEM, "host allocation failed");
   plan->batches.assign(batches, batches + n_batches);
@@ -432,6 +506,59 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
     return rc;
   }
   *out = plan;
+  ft::set_last_error("");
+  return FT_OK;
+}
+
+int run_transfer_batches(const ft_plan_batch* batches, int n_batches, int unknowns, int dtype,
+                         void* coarse, int64_t coarse_elems, void* fine, int64_t fine_elems,
+                         int flags, void* stream) {
+  int dev = -1;
+  int rc = check_batches(batches, n_batches, unknowns, dtype, coarse, coarse_elems, fine,
+                         fine_elems, flags, &dev);
+  if (rc != FT_OK) return rc;
+  int count[2] = {0, 0};
+  for (int i = 0; i < n_batches; ++i)
+    if (batches[i].n_faces > 0) ++count[phase_of(batches[i], flags)];
+  if (count[0] > ft::kScratchSegs || count[1] > ft::kScratchSegs)
+    return pfail(FT_ERR_UNSUPPORTED,
+                 "run_transfer_batches takes at most 128 non-empty batches per phase");
+  ft::PlanSeg* table = nullptr;
+  if ((rc = scratch_on(dev, &table)) != FT_OK) return rc;
+  const hipStream_t s = (hipStream_t)stream;
+  for (int ph = 0; ph < 2; ++ph) {
+    if (count[ph] == 0) continue;
+    ft::PlanSeg* segs = table + ph * ft::kScratchSegs;
+    ft::SegFill fill;
+    fill.first = 0;
+    fill.count = 0;
+    int64_t item = 0;
+    bool interp = false;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n_batches && e == hipSuccess; ++i) {
+      const ft_plan_batch& b = batches[i];
+      if (b.n_faces == 0 || phase_of(b, flags) != ph) continue;
+      fill.seg[fill.count] = make_segment(b, flags, item);
+      item = fill.seg[fill.count].item_end;
+      interp = interp || b.op->direction == FT_INTERPOLATE;
+      if (++fill.count == ft::kFillSegs || fill.first + fill.count == count[ph]) {
+        hipLaunchKernelGGL(ft::fill_segments_kernel, dim3(1), dim3(64), 0, s, segs, fill);
+        e = hipGetLastError();
+        fill.first += fill.count;
+        fill.count = 0;
+      }
+    }
+    if (e != hipSuccess) return phip(e, "run_transfer_batches table fill");
+    // As in plans: a phase without interpolation runs the vector-ALU kernel.
+    const int mode = (dtype != FT_F64 && !interp) ? FT_F32 : dtype;
+    switch (mode) {
+      case FT_F64: e = launch_items<double, 0>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
+      case FT_F32: e = launch_items<float, 0>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
+      case FT_F32_BF16X3: e = launch_items<float, 3>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
+      default: e = launch_items<float, 6>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
+    }
+    if (e != hipSuccess) return phip(e, "run_transfer_batches launch");
+  }
   ft::set_last_error("");
   return FT_OK;
 }
