@@ -482,7 +482,8 @@ def small_u_leg(args, torch, api, wl):
     d-linear and Taylor-2, FP64, both directions.  `call_us`: mean GPU time
     per call between events recorded around each call; `stream_us`: mean
     time per call of `reps` calls issued back to back (host launch cost
-    included); `host_us`: host time to issue one call."""
+    included); `host_us`: host time to issue one call; `graph_us`: mean time
+    per call of `reps` calls replayed from one captured graph."""
     b = wl.workload1(device="cuda:0")
     d = (b.orientation, b.subface, b.coarse_offset, b.fine_offset)
     reps = args.small_u_reps
@@ -517,6 +518,20 @@ def small_u_leg(args, torch, api, wl):
             name = ("interpolate_" if direction == api.FT_INTERPOLATE else "restrict_") + SCHEME_NAMES[scheme]
             out[name] = {"call_us": round(call_us, 2), "stream_us": round(1e3 * a.elapsed_time(z) / reps, 2),
                          "host_us": round(1e6 * (t1 - t0) / reps, 2)}
+            # the same calls replayed from a captured graph: GPU time per call
+            # without the host's launch cost
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, capture_error_mode="relaxed"):
+                for _ in range(reps):
+                    fn()
+            g.replay()
+            torch.cuda.synchronize()
+            a.record()
+            g.replay()
+            z.record()
+            torch.cuda.synchronize()
+            out[name]["graph_us"] = round(1e3 * a.elapsed_time(z) / reps, 2)
+            del g
     return out
 
 
@@ -616,7 +631,7 @@ def headline(result, detail_path):
                 m[label]["interp_t3_ms"] = v["interp_ms"]
         h["mixed"] = m
     if "small_u" in result:
-        h["small_u_latency_us"] = {k_: v["call_us"] for k_, v in result["small_u"].items()
+        h["small_u_latency_us"] = {k_: [v["call_us"], v["graph_us"]] for k_, v in result["small_u"].items()
                                    if isinstance(v, dict)}
     if "batched" in result:
         b = result["batched"]
@@ -827,7 +842,7 @@ def main():
 
     if args.small_u_reps > 0:
         result["small_u"] = small_u_leg(args, torch, api, wl)
-        progress("small-U leg done: " + json.dumps({k_: v["call_us"] for k_, v in result["small_u"].items()
+        progress("small-U leg done: " + json.dumps({k_: v for k_, v in result["small_u"].items()
                                                      if isinstance(v, dict)}))
 
     if args.cpu_faces > 0:

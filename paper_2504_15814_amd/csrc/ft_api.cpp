@@ -398,11 +398,11 @@ int interpolate_faces(const ft_operator* op, int64_t n_faces, const int8_t* orie
   ft::LaunchArgs la{n_faces, orientation, subface, coarse_offset, fine_offset, unknowns, dtype,
                     coarse, coarse_elems, fine, fine_elems, op->d_errors};
   hipError_t e;
-  if (dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6)
-    e = ft::launch_interp_mfma(op, la, ft::LaunchConfig(), dtype == FT_F32_BF16X6 ? 6 : 3,
-                               (hipStream_t)stream);
+  const ft::LaunchConfig cfg;
+  if ((dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6) && unknowns > cfg.small_unknowns[0])
+    e = ft::launch_interp_mfma(op, la, cfg, dtype == FT_F32_BF16X6 ? 6 : 3, (hipStream_t)stream);
   else
-    e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
+    e = ft::launch_apply(op, la, cfg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "interpolate_faces launch");
   return ok();
 }
@@ -433,11 +433,11 @@ int interpolate_patches(const ft_operator* op, int64_t n_faces, const int8_t* or
   ft::LaunchArgs la{n_faces, orientation, subface, coarse_offset, fine_offset, unknowns, dtype,
                     coarse, coarse_elems, fine, fine_elems, op->d_errors, ft::kPatches};
   hipError_t e;
-  if (dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6)
-    e = ft::launch_interp_mfma(op, la, ft::LaunchConfig(), dtype == FT_F32_BF16X6 ? 6 : 3,
-                               (hipStream_t)stream);
+  const ft::LaunchConfig cfg;
+  if ((dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6) && unknowns > cfg.small_unknowns[0])
+    e = ft::launch_interp_mfma(op, la, cfg, dtype == FT_F32_BF16X6 ? 6 : 3, (hipStream_t)stream);
   else
-    e = ft::launch_apply(op, la, ft::LaunchConfig(), (hipStream_t)stream);
+    e = ft::launch_apply(op, la, cfg, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "interpolate_patches launch");
   return ok();
 }

@@ -59,6 +59,114 @@ __device__ inline int64_t logical_block(int xcd_remap) {
   return (b % 8) * per + b / 8;
 }
 
+// Geometry of one (face, anchor) work item: where its stencil cells and its
+// destination rows live.  Returns false when the item has nothing to do: a
+// bad descriptor (counted once per face) or, with p not a multiple of 3, an
+// anchor of the E x E grid that holds no column of this subface.  With p not
+// a multiple of 3 some interpolation rows also belong to the neighbouring
+// fine face (not stored; see `full`).
+struct ItemGeom {
+  int64_t so, dof;         // element offsets of the source / destination face or patch
+  int anchor_cell;         // source cell of the anchor at normal coordinate 0
+  int nstride, sb, sc;     // source strides: normal (signed), tangential b and c
+  int dst_cell0, dstride;  // destination cell of row 0, signed normal stride
+  int db, dc;              // destination tangential strides
+  int dst_b, dst_c;        // destination column of row tb = tc = 0
+  int cls, width, start;   // anchor class and its weight block
+};
+
+template <int DIR, int EC, int DIM>
+__device__ __forceinline__ bool item_geometry(
+    const FT_CONST DevOp* op, const int face, const int e, const int layout,
+    const FT_CONST int8_t* orientation, const FT_CONST int8_t* subface,
+    const FT_CONST int64_t* src_offset, const FT_CONST int64_t* dst_offset, const int U,
+    const int64_t src_elems, const int64_t dst_elems, int* __restrict__ errors, ItemGeom* g) {
+  const int lane = threadIdx.x & 63;
+  const int E = EC > 0 ? EC : op->E;
+  const int eb = DIM == 3 ? e % E : e, ec = DIM == 3 ? e / E : 0;
+  const int p = op->p, k = op->k;
+
+  const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
+  const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
+  // Elements one item may touch: a face buffer, or a whole patch box.
+  const int P = p + 2 * k;
+  const int64_t item_elems =
+      (layout == kFaceBuffers ? (int64_t)(2 * k * p) * (DIM == 3 ? p : 1) : (int64_t)P * P * P) *
+      U;
+  const int64_t so = src_offset[face];
+  const int64_t dof = dst_offset[face];
+  const bool bad = o < 0 || o > (DIM == 3 ? 5 : 3) || s < 0 || s > (DIM == 3 ? 8 : 2) || so < 0 ||
+                   dof < 0 || so > src_elems - item_elems || dof > dst_elems - item_elems;
+  if (bad) {
+    if (e == 0 && lane == 0) atomicAdd(errors, 1);
+    return false;
+  }
+  FaceView sv, dv;
+  if (DIM == 3)
+    transfer_views(DIR, layout, o, p, k, &sv, &dv);
+  else
+    sv = dv = buffer_view2d(o % 2, p, k);
+  int nbase, nsign;
+  normal_map_side(DIR, o < (DIM == 3 ? 3 : 2), k, &nbase, &nsign);
+  const int sb = DIM == 3 ? s % 3 : s, sc = DIM == 3 ? s / 3 : 0;
+
+  // Anchor columns in the source face (anc) and first destination columns
+  // (dst: the fine column of row tb = 0, or the coarse target column).
+  int anc_b, anc_c = 0, dst_b, dst_c = 0;
+  if (DIR == 0) {
+    anc_b = interp_anchor0(sb, p) + eb;
+    dst_b = 3 * anc_b - sb * p;
+    if (DIM == 3) {
+      anc_c = interp_anchor0(sc, p) + ec;
+      dst_c = 3 * anc_c - sc * p;
+    }
+    if (!interp_anchor_valid(anc_b, sb, p) || (DIM == 3 && !interp_anchor_valid(anc_c, sc, p)))
+      return false;
+  } else {
+    dst_b = restrict_anchor0(sb, p) + eb;
+    anc_b = 3 * dst_b + 1 - sb * p;
+    if (DIM == 3) {
+      dst_c = restrict_anchor0(sc, p) + ec;
+      anc_c = 3 * dst_c + 1 - sc * p;
+    }
+    if (!restrict_anchor_valid(dst_b, sb, p) || (DIM == 3 && !restrict_anchor_valid(dst_c, sc, p)))
+      return false;
+  }
+  const int cls = axis_class(anc_b, p) * kAxisClasses + (DIM == 3 ? axis_class(anc_c, p) : 0);
+  g->so = so;
+  g->dof = dof;
+  g->cls = cls;
+  g->width = op->width[cls];
+  g->start = op->start[cls];
+  g->anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
+  g->nstride = nsign * sv.sa;
+  g->sb = sv.sb;
+  g->sc = sv.sc;
+  g->dst_cell0 = dv.base + nbase * dv.sa + dst_b * dv.sb + dst_c * dv.sc;
+  g->dstride = nsign * dv.sa;
+  g->db = dv.sb;
+  g->dc = dv.sc;
+  g->dst_b = dst_b;
+  g->dst_c = dst_c;
+  return true;
+}
+
+// Destination cell of row r of an item, and whether the row is this fine
+// face's (interpolation with p not a multiple of 3 has rows of the
+// neighbouring fine face at the subface edges).
+template <int DIR, int DIM>
+__device__ __forceinline__ int row_cell(const ItemGeom& g, const int r, const int p, bool* mine) {
+  if (DIR == 0) {
+    const int gl = DIM == 3 ? r / 9 : r / 3, tb = DIM == 3 ? (r / 3) % 3 : r % 3;
+    const int tc = DIM == 3 ? r % 3 : 0;
+    *mine = (unsigned)(g.dst_b + tb) < (unsigned)p &&
+            (DIM == 2 || (unsigned)(g.dst_c + tc) < (unsigned)p);
+    return g.dst_cell0 + gl * g.dstride + tb * g.db + tc * g.dc;
+  }
+  *mine = true;
+  return g.dst_cell0 + r * g.dstride;
+}
+
 // DIR 0: interpolation (src = coarse, dst = fine).  DIR 1: restriction
 // (src = fine, dst = coarse).  R rows per anchor; EC anchors per axis (0 = read
 // from the operator); COPY is the exact-copy row (its source is stencil entry
@@ -80,72 +188,20 @@ __device__ __forceinline__ void apply_item(
   const FT_CONST W* weights = cptr(weights_);
   constexpr int kGroup = 4;  // stencil loads in flight per wave before their FMAs
   const int lane = threadIdx.x & 63;
-  const int E = EC > 0 ? EC : op->E;
-  const int eb = DIM == 3 ? e % E : e, ec = DIM == 3 ? e / E : 0;
-  const int p = op->p, k = op->k;
-
-  const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
-  const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
-  // Elements one item may touch: a face buffer, or a whole patch box.
-  const int P = p + 2 * k;
-  const int64_t item_elems =
-      (layout == kFaceBuffers ? (int64_t)(2 * k * p) * (DIM == 3 ? p : 1) : (int64_t)P * P * P) *
-      U;
-  const int64_t so = src_offset[face];
-  const int64_t dof = dst_offset[face];
-  const bool bad = o < 0 || o > (DIM == 3 ? 5 : 3) || s < 0 || s > (DIM == 3 ? 8 : 2) || so < 0 ||
-                   dof < 0 || so > src_elems - item_elems || dof > dst_elems - item_elems;
-  if (bad) {
-    if (e == 0 && lane == 0) atomicAdd(errors, 1);
+  const int p = op->p;
+  ItemGeom g;
+  if (!item_geometry<DIR, EC, DIM>(op, face, e, layout, orientation, subface, src_offset,
+                                   dst_offset, U, src_elems, dst_elems, errors, &g))
     return;
-  }
-  FaceView sv, dv;
-  if (DIM == 3)
-    transfer_views(DIR, layout, o, p, k, &sv, &dv);
-  else
-    sv = dv = buffer_view2d(o % 2, p, k);
-  int nbase, nsign;
-  normal_map_side(DIR, o < (DIM == 3 ? 3 : 2), k, &nbase, &nsign);
-  const int sb = DIM == 3 ? s % 3 : s, sc = DIM == 3 ? s / 3 : 0;
+  const int width = g.width;
+  const int anchor_cell = g.anchor_cell;
+  const int nstride = g.nstride;
+  const int dst_b = g.dst_b, dst_c = g.dst_c;
 
-  // Anchor columns in the source face (anc) and first destination columns
-  // (dst: the fine column of row tb = 0, or the coarse target column).  With
-  // p not a multiple of 3 some anchors of the E x E grid hold no fine column
-  // of this subface (nothing to do) and some interpolation rows belong to the
-  // neighbouring fine face (not stored).
-  int anc_b, anc_c = 0, dst_b, dst_c = 0;
-  if (DIR == 0) {
-    anc_b = interp_anchor0(sb, p) + eb;
-    dst_b = 3 * anc_b - sb * p;
-    if (DIM == 3) {
-      anc_c = interp_anchor0(sc, p) + ec;
-      dst_c = 3 * anc_c - sc * p;
-    }
-    if (!interp_anchor_valid(anc_b, sb, p) || (DIM == 3 && !interp_anchor_valid(anc_c, sc, p)))
-      return;
-  } else {
-    dst_b = restrict_anchor0(sb, p) + eb;
-    anc_b = 3 * dst_b + 1 - sb * p;
-    if (DIM == 3) {
-      dst_c = restrict_anchor0(sc, p) + ec;
-      anc_c = 3 * dst_c + 1 - sc * p;
-    }
-    if (!restrict_anchor_valid(dst_b, sb, p) || (DIM == 3 && !restrict_anchor_valid(dst_c, sc, p)))
-      return;
-  }
-  const int cls = axis_class(anc_b, p) * kAxisClasses + (DIM == 3 ? axis_class(anc_c, p) : 0);
-  const int width = op->width[cls];
-  const int start = op->start[cls];
-  const int anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
-  const int nstride = nsign * sv.sa;
-  // First destination cell of this anchor and the strides of its rows.
-  const int dst_cell0 = dv.base + nbase * dv.sa + dst_b * dv.sb + dst_c * dv.sc;
-  const int dstride = nsign * dv.sa;
-
-  const T* __restrict__ sp = src + so;
-  T* __restrict__ dp = dst + dof;
-  const FT_CONST int* pts = cptr(op->stencil) + start;
-  const FT_CONST W* wts = weights + (int64_t)start * R;
+  const T* __restrict__ sp = src + g.so;
+  T* __restrict__ dp = dst + g.dof;
+  const FT_CONST int* pts = cptr(op->stencil) + g.start;
+  const FT_CONST W* wts = weights + (int64_t)g.start * R;
 
   for (int u0 = 0; u0 < U; u0 += 64) {
     const int u = u0 + lane;
@@ -162,7 +218,7 @@ __device__ __forceinline__ void apply_item(
       for (int j = 0; j < kGroup; ++j) {
         int n, db, dc;
         unpack_point(pts[q + j], &n, &db, &dc);
-        const int cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
+        const int cell = anchor_cell + n * nstride + db * g.sb + dc * g.sc;
         x[j] = A(sp[(int64_t)cell * U + uu]);
       }
       if (COPY >= 0 && q == 0) copy_val = x[0];
@@ -177,7 +233,7 @@ __device__ __forceinline__ void apply_item(
     for (; q < width; ++q) {
       int n, db, dc;
       unpack_point(pts[q], &n, &db, &dc);
-      const int cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
+      const int cell = anchor_cell + n * nstride + db * g.sb + dc * g.sc;
       const A x = A(sp[(int64_t)cell * U + uu]);
       if (COPY >= 0 && q == 0) copy_val = x;
       const FT_CONST W* w = wts + q * R;
@@ -194,18 +250,9 @@ __device__ __forceinline__ void apply_item(
     auto store_rows = [&](auto check) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        int dcell;
-        if (DIR == 0) {
-          const int g = DIM == 3 ? r / 9 : r / 3, tb = DIM == 3 ? (r / 3) % 3 : r % 3;
-          const int tc = DIM == 3 ? r % 3 : 0;
-          if (decltype(check)::value &&
-              ((unsigned)(dst_b + tb) >= (unsigned)p ||
-               (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p)))
-            continue;
-          dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
-        } else {
-          dcell = dst_cell0 + r * dstride;
-        }
+        bool mine;
+        const int dcell = row_cell<DIR, DIM>(g, r, p, &mine);
+        if (decltype(check)::value && !mine) continue;
         // Streaming (non-temporal) stores: the written halo is not re-read by
         // this launch.
         __builtin_nontemporal_store(T(r == COPY ? copy_val : acc[r]), &dp[(int64_t)dcell * U + u]);
@@ -215,6 +262,93 @@ __device__ __forceinline__ void apply_item(
       store_rows(std::false_type{});
     else
       store_rows(std::true_type{});
+  }
+}
+
+// Order this wave's LDS writes before its reads of what other lanes wrote
+// (the slice is private to the wave, so no block barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Copy n values into LDS, lanes over the values, eight loads in flight per
+// lane before their LDS writes.
+template <typename A, typename Load>
+__device__ __forceinline__ void stage_lds(A* __restrict__ to, const int n, const int lane,
+                                          Load load) {
+  constexpr int kBatch = 8;
+  for (int j0 = 0; j0 < n; j0 += 64 * kBatch) {
+    A v[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int j = j0 + 64 * i + lane;
+      v[i] = j < n ? load(j) : A(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int j = j0 + 64 * i + lane;
+      if (j < n) to[j] = v[i];
+    }
+  }
+}
+
+// Few unknowns per cell (Section 6: for PDEs with few unknowns the
+// application strategy decides the speed): with lanes over unknowns most of
+// the wave would idle and every load and store would move a few bytes.
+// Here the anchor's weight block (width x R, contiguous) and all its
+// (stencil point, unknown) source values are loaded at once, lanes over the
+// values, into the wave's LDS slice: ws[q * R + r], then xs[q * U + u].
+// Then lanes run over (row, unknown) outputs and each sums its row over the
+// stencil in stencil order: the same fused multiply-add chain as
+// apply_item, so both bodies give bitwise equal results.  The slice holds
+// width * (R + U) values of A.
+template <int DIR, int R, int COPY, typename T, typename A, typename W, int DIM = 3>
+__device__ __forceinline__ void small_item(
+    const DevOp* __restrict__ op_, const int face, const int e, const int layout,
+    const int8_t* __restrict__ orientation_, const int8_t* __restrict__ subface_,
+    const int64_t* __restrict__ src_offset_, const int64_t* __restrict__ dst_offset_, const int U,
+    const T* __restrict__ src, const int64_t src_elems, T* __restrict__ dst,
+    const int64_t dst_elems, const W* __restrict__ weights, int* __restrict__ errors,
+    A* __restrict__ slice) {
+  const FT_CONST DevOp* op = cptr(op_);
+  const int lane = threadIdx.x & 63;
+  const int p = op->p;
+  ItemGeom g;
+  if (!item_geometry<DIR, 0, DIM>(op, face, e, layout, cptr(orientation_), cptr(subface_),
+                                  cptr(src_offset_), cptr(dst_offset_), U, src_elems, dst_elems,
+                                  errors, &g))
+    return;
+  const T* __restrict__ sp = src + g.so;
+  T* __restrict__ dp = dst + g.dof;
+  const int* __restrict__ pts = op_->stencil + g.start;
+  const W* __restrict__ wts = weights + (int64_t)g.start * R;
+  const int width = g.width;
+  A* __restrict__ ws = slice;
+  A* __restrict__ xs = slice + width * R;
+
+  stage_lds(ws, width * R, lane, [&](int j) { return A(wts[j]); });
+  stage_lds(xs, width * U, lane, [&](int j) {
+    const int q = j / U, u = j - q * U;
+    int n, db, dc;
+    unpack_point(pts[q], &n, &db, &dc);
+    const int cell = g.anchor_cell + n * g.nstride + db * g.sb + dc * g.sc;
+    return A(sp[(int64_t)cell * U + u]);
+  });
+  wave_lds_sync();
+  const int n_out = R * U;
+  for (int o = lane; o < n_out; o += 64) {
+    const int r = o / U, u = o - r * U;
+    bool mine;
+    const int dcell = row_cell<DIR, DIM>(g, r, p, &mine);
+    A acc = A(0);
+    if (r == COPY) {
+      acc = xs[u];  // the exact copy of stencil entry 0
+    } else {
+      for (int q = 0; q < width; ++q) acc = fma(ws[q * R + r], xs[q * U + u], acc);
+    }
+    if (mine) __builtin_nontemporal_store(T(acc), &dp[(int64_t)dcell * U + u]);
   }
 }
 
@@ -236,48 +370,18 @@ __device__ __forceinline__ void mfma_item(
   // the coarse centre itself when k >= 2; with k = 1 no row is a copy.
   constexpr int COPY = DIM == 3 ? (R >= 18 ? 13 : -1) : (R >= 6 ? 4 : -1);
   const int lane = threadIdx.x & 63;
-  const int E = EC > 0 ? EC : op->E;
-  const int eb = DIM == 3 ? e % E : e, ec = DIM == 3 ? e / E : 0;
-  const int p = op->p, k = op->k;
-
-  const int o = __builtin_amdgcn_readfirstlane((int)orientation[face]);
-  const int s = __builtin_amdgcn_readfirstlane((int)subface[face]);
-  const int P = p + 2 * k;
-  const int64_t item_elems =
-      (layout == kFaceBuffers ? (int64_t)(2 * k * p) * (DIM == 3 ? p : 1) : (int64_t)P * P * P) *
-      U;
-  const int64_t so = src_offset[face];
-  const int64_t dof = dst_offset[face];
-  const bool bad = o < 0 || o > (DIM == 3 ? 5 : 3) || s < 0 || s > (DIM == 3 ? 8 : 2) || so < 0 ||
-                   dof < 0 || so > src_elems - item_elems || dof > dst_elems - item_elems;
-  if (bad) {
-    if (e == 0 && lane == 0) atomicAdd(errors, 1);
+  const int p = op->p;
+  ItemGeom g;
+  if (!item_geometry<0, EC, DIM>(op, face, e, layout, orientation, subface, src_offset,
+                                 dst_offset, U, src_elems, dst_elems, errors, &g))
     return;
-  }
-  FaceView sv, dv;
-  if (DIM == 3)
-    transfer_views(0, layout, o, p, k, &sv, &dv);
-  else
-    sv = dv = buffer_view2d(o % 2, p, k);
-  int nbase, nsign;
-  normal_map_side(0, o < (DIM == 3 ? 3 : 2), k, &nbase, &nsign);
-  const int nstride = nsign * sv.sa;
-  const int dstride = nsign * dv.sa;
-  const int sb = DIM == 3 ? s % 3 : s, sc = DIM == 3 ? s / 3 : 0;
-  // Anchor coarse columns and the fine columns of their rows tb = 0 (see
-  // apply_item: with p not a multiple of 3 some anchors are empty and some
-  // rows belong to the neighbouring fine face).
-  const int anc_b = interp_anchor0(sb, p) + eb;
-  const int anc_c = DIM == 3 ? interp_anchor0(sc, p) + ec : 0;
-  if (!interp_anchor_valid(anc_b, sb, p) || (DIM == 3 && !interp_anchor_valid(anc_c, sc, p)))
-    return;
-  const int dst_b = 3 * anc_b - sb * p, dst_c = DIM == 3 ? 3 * anc_c - sc * p : 0;
-  const int cls = axis_class(anc_b, p) * kAxisClasses + (DIM == 3 ? axis_class(anc_c, p) : 0);
-  const int width = op->width[cls];
-  const int start = op->start[cls];
+  const int cls = g.cls;
+  const int width = g.width;
+  const int start = g.start;
   const int nsteps = (width + kMfmaK - 1) / kMfmaK;
-  const int anchor_cell = sv.base + anc_b * sv.sb + anc_c * sv.sc + nbase * sv.sa;
-  const int dst_cell0 = dv.base + nbase * dv.sa + dst_b * dv.sb + dst_c * dv.sc;
+  const int anchor_cell = g.anchor_cell;
+  const int nstride = g.nstride;
+  const int dst_b = g.dst_b, dst_c = g.dst_c;
 
   const FT_CONST bf16x8* wt = cptr(reinterpret_cast<const bf16x8*>(op->wbf16));
   const FT_CONST int* pts = cptr(op->stencil) + start;
@@ -285,11 +389,11 @@ __device__ __forceinline__ void mfma_item(
   if (COPY >= 0) {
     int n, db, dc;
     unpack_point(pts[0], &n, &db, &dc);  // the copy source is entry 0
-    copy_cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
+    copy_cell = anchor_cell + n * nstride + db * g.sb + dc * g.sc;
   }
 
-  const float* __restrict__ sp = src + so;
-  float* __restrict__ dp = dst + dof;
+  const float* __restrict__ sp = src + g.so;
+  float* __restrict__ dp = dst + g.dof;
   for (int u0 = 0; u0 < U; u0 += 64) {
     // Lanes run over 64 unknowns: every stencil cell is one coalesced load.
     // The B operands of the two 32-unknown tiles are then formed in
@@ -313,7 +417,7 @@ __device__ __forceinline__ void mfma_item(
         if (q < width) {
           int n, db, dc;
           unpack_point(pts[q], &n, &db, &dc);
-          const int cell = anchor_cell + n * nstride + db * sv.sb + dc * sv.sc;
+          const int cell = anchor_cell + n * nstride + db * g.sb + dc * g.sc;
           x[j] = sp[(int64_t)cell * U + uu];
         }
       }
@@ -381,13 +485,9 @@ __device__ __forceinline__ void mfma_item(
       auto store_rows = [&](auto check) {
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-          const int g = DIM == 3 ? m / 9 : m / 3, tb = DIM == 3 ? (m / 3) % 3 : m % 3;
-          const int tc = DIM == 3 ? m % 3 : 0;
-          if (decltype(check)::value &&
-              ((unsigned)(dst_b + tb) >= (unsigned)p ||
-               (DIM == 3 && (unsigned)(dst_c + tc) >= (unsigned)p)))
-            continue;
-          const int dcell = dst_cell0 + g * dstride + tb * dv.sb + tc * dv.sc;
+          bool mine;
+          const int dcell = row_cell<0, DIM>(g, m, p, &mine);
+          if (decltype(check)::value && !mine) continue;
           __builtin_nontemporal_store(m == COPY ? xc : rows[m], &dp[(int64_t)dcell * U + u]);
         }
       };

@@ -5,6 +5,16 @@
 
 #include "ft_internal.h"
 
+// Largest unknown count per cell that runs the small-U body: interpolation
+// (27 rows per anchor; the body's two LDS reads per product bound it above
+// this) and restriction (3 rows).
+#ifndef FT_SMALL_UNKNOWNS_INTERP
+#define FT_SMALL_UNKNOWNS_INTERP 8
+#endif
+#ifndef FT_SMALL_UNKNOWNS_RESTRICT
+#define FT_SMALL_UNKNOWNS_RESTRICT 16
+#endif
+
 namespace ft {
 
 struct LaunchArgs {
@@ -32,6 +42,11 @@ struct LaunchConfig {
   // GB per 20,000 faces) and gives restriction ~2 %; not used for float32
   // interpolation, which it slows down.
   int xcd_remap = 1;
+  // Calls with at most this many unknowns per cell run the small-U body
+  // (lanes over stencil points and rows instead of unknowns; every float32
+  // mode then runs on the vector ALUs), per direction.  Plans, which mix
+  // directions, use the interpolation limit.
+  int small_unknowns[2] = {FT_SMALL_UNKNOWNS_INTERP, FT_SMALL_UNKNOWNS_RESTRICT};
 };
 
 hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const LaunchConfig& cfg,

@@ -112,6 +112,85 @@ static hipError_t launch_typed(const ft_operator* op, const Geometry& g, const L
                 : launch_e<1, 3, -1, T, double, double>(op, g, la, d.w64, stream);
 }
 
+// Few unknowns per cell: small_item with a wave-private LDS slice of
+// xs_stride values of A (the anchor's weight block and its source values).
+template <int DIR, int R, int COPY, typename T, typename A, typename W, int DIM>
+__global__ __launch_bounds__(256) void small_kernel(
+    const DevOp* __restrict__ op, const Geometry geo, const int8_t* __restrict__ orientation,
+    const int8_t* __restrict__ subface, const int64_t* __restrict__ src_offset,
+    const int64_t* __restrict__ dst_offset, const int U, const T* __restrict__ src,
+    const int64_t src_elems, T* __restrict__ dst, const int64_t dst_elems,
+    const W* __restrict__ weights, int* __restrict__ errors, const int xs_stride) {
+  extern __shared__ double lds_words[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int anchors = geo.anchors;
+  const int item = (int)logical_block(geo.xcd_remap) * geo.waves_per_block + wave;
+  const int face = item / anchors;
+  if (face >= geo.n_faces) return;
+  A* xs = reinterpret_cast<A*>(lds_words) + wave * xs_stride;
+  small_item<DIR, R, COPY, T, A, W, DIM>(op, face, item - face * anchors, geo.layout, orientation,
+                                         subface, src_offset, dst_offset, U, src, src_elems, dst,
+                                         dst_elems, weights, errors, xs);
+}
+
+template <int DIR, int R, int COPY, typename T, typename A, typename W, int DIM = 3>
+static hipError_t launch_small_one(const ft_operator* op, const Geometry& g0, const LaunchArgs& la,
+                                   const W* weights, hipStream_t stream) {
+  int widest = 0;
+  for (int c = 0; c < kClasses; ++c) widest = std::max(widest, op->blocks[c].width);
+  const int xs_stride = widest * (R + la.U);  // weight block, then source values
+  const size_t lds = (size_t)g0.waves_per_block * xs_stride * sizeof(A);
+  if (lds > 65536) return hipErrorInvalidValue;  // beyond one workgroup's LDS
+  const int anchors = g0.anchors;
+  const int64_t chunk = ((int64_t)1 << 30) / anchors;
+  for (int64_t f0 = 0; f0 < la.n_faces; f0 += chunk) {
+    Geometry g = g0;
+    g.n_faces = std::min<int64_t>(chunk, la.n_faces - f0);
+    const int64_t blocks = (g.n_faces * anchors + g.waves_per_block - 1) / g.waves_per_block;
+    hipLaunchKernelGGL((small_kernel<DIR, R, COPY, T, A, W, DIM>), dim3((unsigned)blocks),
+                       dim3(64 * g.waves_per_block), lds, stream, op->d_devop, g,
+                       la.orientation + f0, la.subface + f0, la.src_offset + f0, la.dst_offset + f0,
+                       la.U, static_cast<const T*>(la.src), la.src_elems, static_cast<T*>(la.dst),
+                       la.dst_elems, weights, la.errors, xs_stride);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T, typename IA>
+static hipError_t launch_small(const ft_operator* op, const Geometry& g, const LaunchArgs& la,
+                               hipStream_t stream) {
+  const DevOp& d = op->dev;
+  const IA* iw;
+  if constexpr (sizeof(IA) == 8) iw = d.w64; else iw = d.w32;
+  const bool inject = op->copy_row == 0;
+  if (op->dim == 2) {
+    if (op->direction == FT_INTERPOLATE) {
+      if (op->k == 1) return launch_small_one<0, 3, -1, T, IA, IA, 2>(op, g, la, iw, stream);
+      if (op->k == 2) return launch_small_one<0, 6, 4, T, IA, IA, 2>(op, g, la, iw, stream);
+      return launch_small_one<0, 9, 4, T, IA, IA, 2>(op, g, la, iw, stream);
+    }
+    if (op->k == 1) return launch_small_one<1, 1, -1, T, double, double, 2>(op, g, la, d.w64, stream);
+    if (op->k == 2)
+      return inject ? launch_small_one<1, 2, 0, T, double, double, 2>(op, g, la, d.w64, stream)
+                    : launch_small_one<1, 2, -1, T, double, double, 2>(op, g, la, d.w64, stream);
+    return inject ? launch_small_one<1, 3, 0, T, double, double, 2>(op, g, la, d.w64, stream)
+                  : launch_small_one<1, 3, -1, T, double, double, 2>(op, g, la, d.w64, stream);
+  }
+  if (op->direction == FT_INTERPOLATE) {
+    if (op->k == 1) return launch_small_one<0, 9, -1, T, IA, IA>(op, g, la, iw, stream);
+    if (op->k == 2) return launch_small_one<0, 18, 13, T, IA, IA>(op, g, la, iw, stream);
+    return launch_small_one<0, 27, 13, T, IA, IA>(op, g, la, iw, stream);
+  }
+  if (op->k == 1) return launch_small_one<1, 1, -1, T, double, double>(op, g, la, d.w64, stream);
+  if (op->k == 2)
+    return inject ? launch_small_one<1, 2, 0, T, double, double>(op, g, la, d.w64, stream)
+                  : launch_small_one<1, 2, -1, T, double, double>(op, g, la, d.w64, stream);
+  return inject ? launch_small_one<1, 3, 0, T, double, double>(op, g, la, d.w64, stream)
+                : launch_small_one<1, 3, -1, T, double, double>(op, g, la, d.w64, stream);
+}
+
 hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const LaunchConfig& cfg,
                         hipStream_t stream) {
   if (cfg.waves_per_block < 1 || cfg.waves_per_block > 4) return hipErrorInvalidValue;
@@ -124,6 +203,11 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
   // slower.
   g.xcd_remap = (op->direction == FT_INTERPOLATE && la.dtype != FT_F64) ? 0 : cfg.xcd_remap;
   g.layout = la.layout;
+  if (la.U <= cfg.small_unknowns[op->direction]) {
+    g.xcd_remap = cfg.xcd_remap;
+    if (la.dtype == FT_F64) return launch_small<double, double>(op, g, la, stream);
+    return launch_small<float, float>(op, g, la, stream);
+  }
   if (la.dtype == FT_F64) return launch_typed<double, double>(op, g, la, stream);
   // FT_F32 and (for restriction) the split-bfloat16 modes: float32 storage.
   return launch_typed<float, float>(op, g, la, stream);

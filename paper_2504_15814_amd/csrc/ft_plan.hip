@@ -177,6 +177,80 @@ __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restric
   }
 }
 
+// One work item of a plan segment with the small-U body (few unknowns per
+// cell): every mode runs on the vector ALUs, as the per-batch calls do.
+template <typename T, int KIND>
+__device__ __forceinline__ void plan_small_item(const PlanSeg* __restrict__ S, const int face_,
+                                                const int e_, const int U, T* __restrict__ coarse,
+                                                const int64_t coarse_elems, T* __restrict__ fine,
+                                                const int64_t fine_elems, double* xs_words) {
+  const int face = __builtin_amdgcn_readfirstlane(face_);
+  const int e = __builtin_amdgcn_readfirstlane(e_);
+  const DevOp* __restrict__ op = S->op;
+  const FT_CONST DevOp* cop = cptr(op);
+  if constexpr (KIND == kInterp9 || KIND == kInterp18 || KIND == kInterp27) {
+    constexpr int R = KIND == kInterp9 ? 9 : (KIND == kInterp18 ? 18 : 27);
+    constexpr int COPY = R >= 18 ? 13 : -1;
+    small_item<0, R, COPY, T, T, T>(
+        op, face, e, S->layout, S->orientation, S->subface, S->coarse_offset, S->fine_offset, U,
+        coarse, coarse_elems, fine, fine_elems,
+        (const T*)(sizeof(T) == 8 ? (const void*)cop->w64 : (const void*)cop->w32), S->errors,
+        reinterpret_cast<T*>(xs_words));
+  } else {
+    constexpr int R = KIND == kRestrict1Plain
+                          ? 1
+                          : ((KIND == kRestrict2Inject || KIND == kRestrict2Plain) ? 2 : 3);
+    constexpr int COPY = (KIND == kRestrict2Inject || KIND == kRestrict3Inject) ? 0 : -1;
+    small_item<1, R, COPY, T, double, double>(op, face, e, S->layout, S->orientation, S->subface,
+                                              S->fine_offset, S->coarse_offset, U, fine,
+                                              fine_elems, coarse, coarse_elems, cop->w64,
+                                              S->errors, xs_words);
+  }
+}
+
+// The non-persistent plan launch with the small-U body; each wave owns
+// xs_stride words of the block's dynamic LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void plan_small_kernel(const PlanSeg* __restrict__ segs,
+                                                         const int nseg, const int64_t total,
+                                                         const int wpb, const int remap,
+                                                         const int U, T* __restrict__ coarse,
+                                                         const int64_t coarse_elems,
+                                                         T* __restrict__ fine,
+                                                         const int64_t fine_elems,
+                                                         const int xs_stride) {
+  extern __shared__ double plan_lds[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t b = blockIdx.x;
+  if (remap) {
+    const int64_t nb = gridDim.x, per = nb / 8, full = per * 8;
+    if (b < full) b = (b % 8) * per + b / 8;
+  }
+  const int64_t it = b * wpb + wave;
+  if (it >= total) return;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (it >= segs[mid].item_end) lo = mid + 1; else hi = mid;
+  }
+  const PlanSeg* __restrict__ S = segs + __builtin_amdgcn_readfirstlane(lo);
+  const int local = (int)(it - S->item0);
+  const int anchors = S->anchors;
+  const int face = local / anchors;
+  const int e = local - face * anchors;
+  double* xs = plan_lds + wave * xs_stride;
+  switch (S->kind) {
+    case kInterp18: plan_small_item<T, kInterp18>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kInterp27: plan_small_item<T, kInterp27>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict2Inject: plan_small_item<T, kRestrict2Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict2Plain: plan_small_item<T, kRestrict2Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict3Inject: plan_small_item<T, kRestrict3Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kInterp9: plan_small_item<T, kInterp9>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict1Plain: plan_small_item<T, kRestrict1Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    default: plan_small_item<T, kRestrict3Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Allocation-free fused launch (run_transfer_batches): the segment tables of
 // one call live in `scratch`, a fixed array of this library in device memory
@@ -230,6 +304,7 @@ struct ft_plan {
   int nseg[2] = {0, 0};
   int64_t total[2] = {0, 0};
   bool interp[2] = {false, false};  // the phase holds interpolation segments
+  int widest = 0;                   // widest weight block of any batch's operator
 };
 
 struct ft_graph {
@@ -348,6 +423,33 @@ ft::PlanSeg make_segment(const ft_plan_batch& b, int flags, int64_t item0) {
   return sgm;
 }
 
+// Widest weight block over the batches' operators (LDS of the small-U body).
+int widest_block(const ft_plan_batch* batches, int n_batches) {
+  int w = 0;
+  for (int i = 0; i < n_batches; ++i)
+    for (int c = 0; c < ft::kClasses; ++c) w = std::max(w, batches[i].op->blocks[c].width);
+  return w;
+}
+
+// Small-U launch of one phase: one wave per work item (the persistent form
+// and the matrix-core bodies are not used for few unknowns).
+template <typename T>
+hipError_t launch_small_items(const ft::PlanSeg* segs, int nseg, int64_t total, int wpb, int remap,
+                              int U, int widest, void* coarse, int64_t coarse_elems, void* fine,
+                              int64_t fine_elems, hipStream_t stream) {
+  const int64_t blocks = (total + wpb - 1) / wpb;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  // one slice per wave: the weight block (at most 27 rows) and the source
+  // values, counted in doubles (float slices use half of it)
+  const int xs_stride = widest * (27 + U);
+  const size_t lds = (size_t)wpb * xs_stride * sizeof(double);
+  if (lds > 65536) return hipErrorInvalidValue;  // beyond one workgroup's LDS
+  hipLaunchKernelGGL((ft::plan_small_kernel<T>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
+                     stream, segs, nseg, total, wpb, remap, U, static_cast<T*>(coarse),
+                     coarse_elems, static_cast<T*>(fine), fine_elems, xs_stride);
+  return hipGetLastError();
+}
+
 // Build and upload the segment tables of both phases in both orders.
 int upload_tables(ft_plan* plan) {
   auto tables = std::make_shared<ft::PlanTables>();
@@ -422,6 +524,19 @@ int run_plan(const ft_plan* plan, hipStream_t stream) {
     // (fewer registers, more waves per SIMD).
     const int dtype = (plan->dtype != FT_F64 && !plan->interp[ph]) ? FT_F32 : plan->dtype;
     hipError_t e;
+    if (plan->U <= ft::LaunchConfig().small_unknowns[0]) {
+      const ft::PlanSeg* segs = plan->tables->d_segs[ph][heavy_of(plan->schedule)];
+      const int wpb = wpb_of(plan->schedule), remap = remap_of(plan->schedule);
+      e = plan->dtype == FT_F64
+              ? launch_small_items<double>(segs, plan->nseg[ph], plan->total[ph], wpb, remap, plan->U,
+                                           plan->widest, plan->coarse, plan->coarse_elems,
+                                           plan->fine, plan->fine_elems, stream)
+              : launch_small_items<float>(segs, plan->nseg[ph], plan->total[ph], wpb, remap, plan->U,
+                                          plan->widest, plan->coarse, plan->coarse_elems,
+                                          plan->fine, plan->fine_elems, stream);
+      if (e != hipSuccess) return phip(e, "run_transfer_plan launch");
+      continue;
+    }
     switch (dtype) {
       case FT_F64: e = launch_phase<double, 0>(plan, ph, stream); break;
       case FT_F32: e = launch_phase<float, 0>(plan, ph, stream); break;
@@ -500,6 +615,7 @@ int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknown
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     plan->n_cu = ncu;
   plan->schedule = 4 | (1 << 8);  // 4 waves per block, one wave per work item
+  plan->widest = widest_block(batches, n_batches);
   const int rc = upload_tables(plan);
   if (rc != FT_OK) {
     delete plan;  // releases whatever tables were uploaded
@@ -549,6 +665,15 @@ int run_transfer_batches(const ft_plan_batch* batches, int n_batches, int unknow
       }
     }
     if (e != hipSuccess) return phip(e, "run_transfer_batches table fill");
+    if (unknowns <= ft::LaunchConfig().small_unknowns[0]) {
+      const int widest = widest_block(batches, n_batches);
+      e = dtype == FT_F64 ? launch_small_items<double>(segs, count[ph], item, 4, 0, unknowns, widest,
+                                                       coarse, coarse_elems, fine, fine_elems, s)
+                          : launch_small_items<float>(segs, count[ph], item, 4, 0, unknowns, widest,
+                                                      coarse, coarse_elems, fine, fine_elems, s);
+      if (e != hipSuccess) return phip(e, "run_transfer_batches launch");
+      continue;
+    }
     // As in plans: a phase without interpolation runs the vector-ALU kernel.
     const int mode = (dtype != FT_F64 && !interp) ? FT_F32 : dtype;
     switch (mode) {

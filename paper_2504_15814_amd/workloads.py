@@ -255,6 +255,19 @@ def workload1(device="cpu", dtype=torch.float64):
     return batch
 
 
+def pair_faces(n, p, k, U, seed, device="cpu", dtype=torch.float64):
+    """n faces with o = f mod 6 and s = (f div 6) mod 9 (every orientation /
+    subface pair once n >= 54), bump fields plus 1e-3 noise."""
+    gen = torch.Generator().manual_seed(seed)
+    f = torch.arange(n)
+    orient, sub = f % 6, (f // 6) % 9
+    origin = face_origins(gen, orient, p)
+    fieldfn = bump_field(gen, U)
+    batch = _contiguous_batch(orient, sub, p, k, U, dtype, device, origin)
+    fill_buffers(batch, fieldfn, noise_sigma=1e-3, gen=gen, noise_scale=fieldfn.scale)
+    return batch
+
+
 def uniform_faces(n, p, k, U, seed, device="cpu", dtype=torch.float64, scaled=False, noise=1e-3):
     """n faces with uniform orientation and subface, bump fields plus noise."""
     gen = torch.Generator().manual_seed(seed)
