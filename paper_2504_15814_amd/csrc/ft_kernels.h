@@ -15,16 +15,6 @@
 #define FT_SMALL_UNKNOWNS_RESTRICT 16
 #endif
 
-// Interpolation waves walk a whole row of anchors of one face (1) or take one
-// anchor each (0).
-#ifndef FT_ROW_WALK
-#define FT_ROW_WALK 0
-#endif
-// XCD-contiguous block numbering for float32 interpolation.
-#ifndef FT_F32_INTERP_REMAP
-#define FT_F32_INTERP_REMAP 0
-#endif
-
 namespace ft {
 
 struct LaunchArgs {
@@ -46,10 +36,7 @@ struct LaunchArgs {
 // Tunable launch shape (schedules never change the per-output summation
 // order, so every shape gives bitwise identical results).
 struct LaunchConfig {
-#ifndef FT_APPLY_WPB
-#define FT_APPLY_WPB 4
-#endif
-  int waves_per_block = FT_APPLY_WPB;  // 1..4
+  int waves_per_block = 4;  // 1..4 (1 and 2 are 1-8 % slower)
   // Consecutive blocks on one XCD, so that the anchors of a face share one
   // L2: halves the float64 interpolation's L2 misses (Taylor-3: 1.49 -> 0.75
   // GB per 20,000 faces) and gives restriction ~2 %; not used for float32

@@ -32,17 +32,6 @@ __global__ __launch_bounds__(256) void apply_kernel(
   const int anchors = DIM == 3 ? E * E : E;
   // Launches are split on the host so that items fit in 31 bits.
   const int item = (int)logical_block(geo.xcd_remap) * geo.waves_per_block + wave;
-  if (FT_ROW_WALK && DIR == 0 && DIM == 3) {
-    // item = (face, anchor row ec); the wave walks the row's E anchors
-    const int face = item / E;
-    if (face >= geo.n_faces) return;
-    const int ec = item - face * E;
-    for (int eb = 0; eb < E; ++eb)
-      apply_item<DIR, R, EC, COPY, T, A, W, DIM>(op, face, ec * E + eb, geo.layout, orientation,
-                                                 subface, src_offset, dst_offset, U, src, src_elems,
-                                                 dst, dst_elems, weights, errors);
-    return;
-  }
   const int face = item / anchors;
   if (face >= geo.n_faces) return;
   apply_item<DIR, R, EC, COPY, T, A, W, DIM>(op, face, item - face * anchors, geo.layout, orientation,
@@ -54,13 +43,12 @@ template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W, 
 static hipError_t launch_one(const ft_operator* op, const Geometry& g0, const LaunchArgs& la,
                              const W* weights, hipStream_t stream) {
   const int anchors = DIM == 3 ? op->E * op->E : op->E;
-  const int per_face = (FT_ROW_WALK && DIR == 0 && DIM == 3) ? op->E : anchors;  // waves per face
   // Split so that (faces in a launch) x anchors stays below 2^30.
   const int64_t chunk = ((int64_t)1 << 30) / anchors;
   for (int64_t f0 = 0; f0 < la.n_faces; f0 += chunk) {
     Geometry g = g0;
     g.n_faces = std::min<int64_t>(chunk, la.n_faces - f0);
-    const int64_t items = g.n_faces * per_face;
+    const int64_t items = g.n_faces * anchors;
     const int64_t blocks = (items + g.waves_per_block - 1) / g.waves_per_block;
     hipLaunchKernelGGL((apply_kernel<DIR, R, EC, COPY, T, A, W, DIM>), dim3((unsigned)blocks),
                        dim3(64 * g.waves_per_block), 0, stream, op->d_devop, g, la.orientation + f0,
@@ -213,9 +201,7 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
   // XCD-contiguous numbering: restriction 2.5 % faster, float64
   // interpolation unchanged (half the L2 misses), float32 interpolation 3-5 %
   // slower.
-  g.xcd_remap = (op->direction == FT_INTERPOLATE && la.dtype != FT_F64 && !FT_F32_INTERP_REMAP)
-                    ? 0
-                    : cfg.xcd_remap;
+  g.xcd_remap = (op->direction == FT_INTERPOLATE && la.dtype != FT_F64) ? 0 : cfg.xcd_remap;
   g.layout = la.layout;
   if (la.U <= cfg.small_unknowns[op->direction]) {
     g.xcd_remap = cfg.xcd_remap;

@@ -25,16 +25,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   const int E = EC > 0 ? EC : op->E;
   const int anchors = DIM == 3 ? E * E : E;
   const int item = (int)logical_block(xcd_remap) * waves_per_block + wave;
-  if (FT_ROW_WALK && DIM == 3) {
-    // item = (face, anchor row ec); the wave walks the row's E anchors
-    const int face = item / E;
-    if (face >= n_faces) return;
-    const int ec = item - face * E;
-    for (int eb = 0; eb < E; ++eb)
-      mfma_item<R, EC, TERMS, DIM>(op, face, ec * E + eb, layout, orientation, subface, src_offset,
-                                   dst_offset, U, src, src_elems, dst, dst_elems, errors);
-    return;
-  }
   const int face = item / anchors;
   if (face >= n_faces) return;
   mfma_item<R, EC, TERMS, DIM>(op, face, item - face * anchors, layout, orientation, subface,
@@ -48,15 +38,14 @@ static hipError_t launch_mfma_one(const ft_operator* op, const LaunchArgs& la,
   const int64_t chunk = ((int64_t)1 << 30) / anchors;
   for (int64_t f0 = 0; f0 < la.n_faces; f0 += chunk) {
     const int64_t nf = std::min<int64_t>(chunk, la.n_faces - f0);
-    const int per_face = (FT_ROW_WALK && DIM == 3) ? op->E : anchors;  // waves per face
-    const int64_t blocks = (nf * per_face + cfg.waves_per_block - 1) / cfg.waves_per_block;
+    const int64_t blocks = (nf * anchors + cfg.waves_per_block - 1) / cfg.waves_per_block;
     hipLaunchKernelGGL((interp_mfma_kernel<R, EC, TERMS, DIM>), dim3((unsigned)blocks),
                        dim3(64 * cfg.waves_per_block), 0, stream, op->d_devop, nf,
                        cfg.waves_per_block, la.orientation + f0, la.subface + f0,
                        la.src_offset + f0, la.dst_offset + f0, la.U,
                        static_cast<const float*>(la.src), la.src_elems,
                        static_cast<float*>(la.dst), la.dst_elems, la.errors, la.layout,
-                       FT_F32_INTERP_REMAP ? cfg.xcd_remap : 0);
+                       0 /* XCD-contiguous numbering: 2-5 % slower here */);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
