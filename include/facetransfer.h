@@ -389,8 +389,11 @@ int transfer_plan_get_schedule(const ft_plan* plan, int64_t* schedule);
 
 /* Autotuner: run the plan `reps` times under each candidate schedule (after
  * one warm-up run), time it with HIP events on `stream`, keep the fastest,
- * and report it and its mean time in milliseconds.  The runs write the
- * plan's outputs like run_transfer_plan.  Synchronises the stream. */
+ * and report it and its mean time in milliseconds.  The candidates are the
+ * one-wave-per-item schedules (2 or 4 waves per block, xcd_remap and
+ * heavy_first on or off); persistent schedules stay available through
+ * transfer_plan_set_schedule.  The runs write the plan's outputs like
+ * run_transfer_plan.  Synchronises the stream. */
 int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_schedule,
                            double* best_ms);
 

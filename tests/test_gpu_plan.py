@@ -1,4 +1,4 @@
-"""Plans (one persistent launch over an uneven mix), schedules, the autotuner
+"""Plans (one fused launch over an uneven mix), schedules, the autotuner
 and HIP-graph capture, all through the C ABI.
 
 A plan runs the same per-item code as the per-batch kernels, so its output
@@ -120,7 +120,7 @@ def test_autotune_picks_a_valid_schedule(mixed32):
     plan = api.build_transfer_plan(batches_of(mixed32, ops), mixed32.U, coarse, fine, mode=api.FT_F32)
     best, ms = plan.autotune(reps=2)
     sch = api.unpack_schedule(best)
-    assert sch["waves_per_block"] in (2, 4) and sch["blocks_per_cu"] in (1, 2, 4, 8, 16)
+    assert sch["waves_per_block"] in (2, 4) and sch["blocks_per_cu"] == 1 and sch["persistent"] == 0
     assert plan.schedule == best and ms > 0
     rc, rf = per_batch_reference(mixed32, ops, api.FT_F32)
     plan.run()
