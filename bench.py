@@ -539,8 +539,8 @@ def cpu_baseline(batch, n_faces, torch):
     """The FP64 oracle on the host, on the first n_faces faces of the same
     batch; operators are built before timing (the paper times repeated calls
     without reallocation) and their build is timed separately.  Median of
-    three runs with the host BLAS threads, plus one single-thread run on a
-    tenth of the sample."""
+    three runs with the host BLAS threads, plus the median of three
+    single-thread runs on a tenth of the sample."""
     import statistics
 
     import threadpoolctl
@@ -576,7 +576,7 @@ def cpu_baseline(batch, n_faces, torch):
     dt = statistics.median(run(n_faces) for _ in range(3))
     n1 = max(1, n_faces // 10)
     with threadpoolctl.threadpool_limits(1):
-        dt1 = run(n1)
+        dt1 = statistics.median(run(n1) for _ in range(3))
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -591,7 +591,7 @@ def cpu_baseline(batch, n_faces, torch):
         "sample": f"first {n_faces} of {batch.n} faces, all 3 schemes x restrict+interpolate, "
                   f"median of 3 runs {dt:.1f} s wall with {threads} BLAS threads",
         "single_thread_value": per_face * n1 / dt1,
-        "single_thread_sample": f"first {n1} faces, {dt1:.1f} s wall",
+        "single_thread_sample": f"first {n1} faces, median of 3 runs {dt1:.1f} s wall",
         "operator_build_s": build_s,
         "host": {"cpu": cpu_model, "nproc": os.cpu_count()},
     }
