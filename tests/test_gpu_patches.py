@@ -304,25 +304,73 @@ def test_patch_transfer_bad_descriptors_and_empty():
     api.copy_patch_halos(p, k, e8, e64, e64, U, fine)
 
 
+def _patch_region(direction, p, k, U, b, dst_len, dev):
+    """Device mask of every element the patch transfer of the whole batch
+    writes: per (orientation, subface) the elements one transfer changes in
+    a sentinel patch box (oracle), placed at each face's destination offset."""
+    P3U = b.patch_elems
+    o_all, s_all = b.orientation.cpu().numpy(), b.subface.cpu().numpy()
+    offs = (b.fine_offset if direction == 0 else b.coarse_offset)
+    mask = torch.zeros(dst_len, dtype=torch.bool, device=dev)
+    rng = np.random.default_rng(1)
+    for o, s in sorted(set(zip(o_all.tolist(), s_all.tolist()))):
+        src = rng.standard_normal(P3U)
+        box = np.full(P3U, SENTINEL)
+        if direction == 0:
+            out = opt.interpolate_patches(oracle.TAYLOR3, p, k, [o], [s], [0], [0], U, src, box)
+        else:
+            out = opt.restrict_patches(oracle.TAYLOR3, p, k, [o], [s], [0], [0], U, src, box)
+        loc = torch.from_numpy(np.flatnonzero(out != SENTINEL)).to(dev)
+        faces = torch.from_numpy(np.flatnonzero((o_all == o) & (s_all == s))).to(dev)
+        for c0 in range(0, faces.numel(), 512):
+            mask[(offs[faces[c0:c0 + 512]][:, None] + loc[None, :]).reshape(-1)] = True
+    return mask
+
+
 def test_full_size_patch_transfer_sampled():
-    """2,000 hanging faces at p=9, k=3, U=59 in float64 (the benchmark's
-    patch configuration), nine per coarse face: sampled faces against the
-    oracle, every face against the unfused GPU composition."""
+    """The benchmark's patch configuration: 6,003 hanging faces at p=9, k=3,
+    U=59 in float64, nine per coarse face.  Every face: the fused step
+    equals the unfused GPU composition bit for bit, and, on the device, each
+    direction writes every element of its region and nothing else; sampled
+    faces against the oracle."""
+    from tests import gpu_helpers as gh
+
     dev = require_gpu()
     p, k, U = 9, 3, 59
-    b = patch_transitions(2000, p, k, U, seed=15814 + 6, device=dev, faces_per_coarse=9)
+    b = patch_transitions(6003, p, k, U, seed=15814 + 6, device=dev, faces_per_coarse=9)
     iop = api.build_transfer_operator(0, oracle.TAYLOR3, p, k)
     rop = api.build_transfer_operator(1, oracle.TAYLOR3, p, k)
+    d = (b.orientation, b.subface, b.coarse_offset, b.fine_offset)
     fine, coarse = b.fine.clone(), b.coarse.clone()
-    api.restrict_patches(rop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, fine, coarse)
-    api.interpolate_patches(iop, b.orientation, b.subface, b.coarse_offset, b.fine_offset, U, coarse, fine)
+    api.restrict_patches(rop, *d, U, fine, coarse)
+    api.interpolate_patches(iop, *d, U, coarse, fine)
     rc, rf = b.coarse.clone(), b.fine.clone()
     unfused_restrict(rop, b, rf, rc, 9)
     unfused_interpolate(iop, b, rc, rf)
     torch.cuda.synchronize()
     assert torch.equal(rc, coarse) and torch.equal(rf, fine)
+    assert rop.errors() == 0 and iop.errors() == 0
+    del rc, rf
+    # each direction alone on sentinel-filled regions (restriction reads only
+    # fine patches, interpolation only coarse ones)
+    cmask = _patch_region(1, p, k, U, b, b.coarse.numel(), dev)
+    cs = b.coarse.clone()
+    cs[cmask] = SENTINEL
+    cb = cs.clone()
+    api.restrict_patches(rop, *d, U, b.fine, cs)
+    torch.cuda.synchronize()
+    gh.check_written_region(cs, cb, cmask)
+    del cs, cb, cmask
+    fmask = _patch_region(0, p, k, U, b, b.fine.numel(), dev)
+    fs = b.fine.clone()
+    fs[fmask] = SENTINEL
+    fb = fs.clone()
+    api.interpolate_patches(iop, *d, U, b.coarse, fs)
+    torch.cuda.synchronize()
+    gh.check_written_region(fs, fb, fmask)
+    del fs, fb, fmask
     P3U = b.patch_elems
-    for i in (0, 4, 999, 1998):
+    for i in (0, 4, 2999, 6002):
         c0 = int(b.coarse_offset[i])
         f0 = int(b.fine_offset[i])
         o, s = [int(b.orientation[i])], [int(b.subface[i])]
