@@ -340,10 +340,11 @@ typedef struct ft_plan_batch {
 } ft_plan_batch;
 
 /* Build a plan over n_batches batches (the batches[] array is copied; the
- * device arrays and buffers must stay valid while the plan is used).
+ * operators, device arrays and buffers must stay valid while the plan or a
+ * graph captured from it is used).
  * dtype as for interpolate_faces; restriction batches of the FT_F32_BF16X*
  * types run as FT_F32.  The schedule starts at a default and can be tuned
- * with transfer_plan_autotune.  Allocates a small device table.
+ * with transfer_plan_autotune.  Allocates its small device segment tables.
  * Errors: FT_ERR_INVALID (null pointers, n_batches < 1, operators of another
  * device), FT_ERR_UNSUPPORTED (dtype, unknowns), FT_ERR_NOMEM, FT_ERR_HIP. */
 int build_transfer_plan(const ft_plan_batch* batches, int n_batches, int unknowns, int dtype,
@@ -400,7 +401,10 @@ int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_
 int destroy_transfer_plan(ft_plan* plan);
 
 /* Capture `steps` consecutive runs of the plan into one HIP graph on a
- * library-owned stream and instantiate it. */
+ * library-owned stream and instantiate it.  The graph holds the plan's
+ * device segment tables (uploaded once, in both segment orders, when the
+ * plan is built): it stays valid after the plan's schedule changes and after
+ * destroy_transfer_plan, as long as the operators and buffers live. */
 int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out);
 
 /* Launch a captured graph on `stream`. */
