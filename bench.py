@@ -29,7 +29,8 @@ SCHEME_NAMES = {1: "dlinear", 2: "taylor2", 3: "taylor3"}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="timed steps (the paper times each method over 100 runs)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--faces", type=int, default=20000)
     ap.add_argument("--cpu-faces", type=int, default=8000,
