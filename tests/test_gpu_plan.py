@@ -298,3 +298,46 @@ def test_full_size_uneven_mix_sampled(dev):
             want = W @ x
             bound = 21 * 2.0**-24 * (np.abs(W) @ np.abs(x)) + 2.0**-24 * np.abs(want)
             assert np.all(np.abs(got - want) <= bound)
+
+
+@pytest.mark.parametrize("U,mode", [(3, None), (3, api.FT_F32_BF16X6), (8, api.FT_F32), (12, None),
+                                    (12, api.FT_F32_BF16X3)])
+def test_plan_at_few_unknowns(dev, U, mode):
+    """Uneven mixes at few unknowns per cell: up to U = 8 the plan runs the
+    small-U body for every item (so does every per-batch call); at U = 12 the
+    plan keeps lanes over unknowns while per-batch restriction takes the
+    small-U body.  Either way the plan equals the per-batch calls bit for
+    bit, and two faces per group match the oracle (float64: 1e-12; float32:
+    the vector-ALU bound up to U = 8, the mode's bound above)."""
+    dtype = torch.float64 if mode is None else torch.float32
+    mb = wl.workload4(n_faces=700, device=dev, dtype=dtype, seed=400 + U, U=U, k_values=(1, 2, 3),
+                      p_values=(6, 8, 12))
+    ops = build_ops(mb)
+    rc, rf = per_batch_reference(mb, ops, mode)
+    _, pc, pf = run_plan(mb, ops, mode)
+    assert torch.equal(pc, rc) and torch.equal(pf, rf)
+    for op in ops.values():
+        assert op.errors() == 0
+    coarse_in, fine_in = mb.coarse.double().cpu().numpy(), mb.fine.double().cpu().numpy()
+    pc_np, pf_np = pc.double().cpu().numpy(), pf.double().cpu().numpy()
+    co, fo = mb.coarse_offset.cpu().numpy(), mb.fine_offset.cpu().numpy()
+    orient, sub = mb.orientation.cpu().numpy(), mb.subface.cpu().numpy()
+    c_interp = {None: 0.0, api.FT_F32: 35 * 2.0**-24, api.FT_F32_BF16X6: 35 * 2.0**-24,
+                api.FT_F32_BF16X3: 3 * 2.0**-16 + 9 * 2.0**-24}[mode]
+    for (d, sch, p, k), idx in mb.groups().items():
+        for f in idx[:2].tolist():
+            rows, W = oracle.transfer_operator(d, sch, p, k, int(orient[f]), int(sub[f]))
+            ncell = 2 * k * p * p
+            if d == 0:
+                x = coarse_in[co[f]:co[f] + ncell * U].reshape(ncell, U)
+                got = pf_np[fo[f]:fo[f] + ncell * U].reshape(ncell, U)[rows]
+            else:
+                x = fine_in[fo[f]:fo[f] + ncell * U].reshape(ncell, U)
+                got = pc_np[co[f]:co[f] + ncell * U].reshape(ncell, U)[rows]
+            want = W @ x
+            if mode is None:
+                assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+            else:
+                c = c_interp if d == 0 else 0.0  # restriction sums in float64
+                bound = (c + 1e-13) * (np.abs(W) @ np.abs(x)) + 1.001 * 2.0**-24 * np.abs(want)
+                assert np.all(np.abs(got - want) <= bound)
