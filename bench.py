@@ -208,7 +208,9 @@ def mesh_leg(args, torch, api, wl):
     coarse faces and then interpolates all fine halos from them.  Plain FP64
     (two launches per step, eager) versus the mixed form (float32 plan,
     split-bfloat16 matrix-core interpolation with compensation) with all
-    steps captured in one HIP graph."""
+    steps captured in one HIP graph, and the mixed-storage form (float64
+    fine data restricted into float32 coarse faces, six-term interpolation
+    into float32 fine halos; two plans per step in one graph)."""
     mf = wl.workload5(n_meshes=args.mesh_meshes, device="cuda:0", dtype=torch.float64)
     U, steps = mf.U, args.mesh_steps
     rop = api.build_transfer_operator(api.FT_RESTRICT, 3, mf.p, mf.k)
@@ -258,6 +260,40 @@ def mesh_leg(args, torch, api, wl):
         return a.elapsed_time(b) / steps, best
 
     ms_mixed, best = graph_ms(plan)
+    del plan, c32, f32
+    # Mixed storage: restriction reads the float64 fine data and writes
+    # float32 coarse faces (one rounding of the FP64 result), interpolation
+    # runs in six split terms into float32 fine halo buffers: two plans per
+    # step, all steps in one graph.
+    cs, hs = mf.coarse.float(), mf.fine.float()
+    rplan = api.build_transfer_plan([(rop, *d)], U, cs, mf.fine, mode=api.FT_F64_TO_F32)
+    iplan = api.build_transfer_plan([(iop, *d)], U, cs, hs, mode=api.FT_F32_BF16X6)
+    rplan.run()
+    iplan.run()
+    # FP64 step on the same stored inputs (float64 fine, float32-rounded coarse)
+    sc_c = mf.coarse.float().double()
+    sc_f = mf.fine.clone()
+    api.restrict_faces(rop, *d, U, sc_f, sc_c)
+    api.interpolate_faces(iop, *d, U, sc_c, sc_f)
+    torch.cuda.synchronize()
+    serr = max(float((cs.double() - ref1_c).abs().max() / ref1_c.abs().max()),
+               float((hs.double() - ref1_f).abs().max() / ref1_f.abs().max()))
+    skerr = max(float((cs.double() - sc_c).abs().max() / sc_c.abs().max()),
+                float((hs.double() - sc_f).abs().max() / sc_f.abs().max()))
+    del sc_c, sc_f
+    rbest, _ = rplan.autotune(reps=3)
+    ibest, _ = iplan.autotune(reps=3)
+    sg = api.transfer_plans_capture([rplan, iplan], steps=steps)
+    sg.launch()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    z = torch.cuda.Event(enable_timing=True)
+    a.record()
+    sg.launch()
+    z.record()
+    torch.cuda.synchronize()
+    ms_storage = a.elapsed_time(z) / steps
+    del sg, rplan, iplan, cs, hs
     # the FP64 step as a plan with all steps in one graph as well
     plan64 = api.build_transfer_plan([(rop, *d), (iop, *d)], U, c64, f64, flags=api.FT_PLAN_RESTRICT_FIRST)
     ms64_graph, _ = graph_ms(plan64)
@@ -272,7 +308,12 @@ def mesh_leg(args, torch, api, wl):
             "mixed_value": produced / (ms_mixed * 1e-3), "f64_value": produced / (ms64 * 1e-3),
             "speedup": ms64 / ms_mixed, "mixed_max_rel_err_one_step": err,
             "mixed_kernel_max_rel_err_one_step": kerr,
-            "schedule": api.unpack_schedule(best)}
+            "schedule": api.unpack_schedule(best),
+            "f64_restrict_graph_ms_per_step": ms_storage,
+            "f64_restrict_speedup_vs_f64_plan_graph": ms64_graph / ms_storage,
+            "f64_restrict_max_rel_err_one_step": serr,
+            "f64_restrict_kernel_max_rel_err_one_step": skerr,
+            "f64_restrict_schedules": [api.unpack_schedule(rbest), api.unpack_schedule(ibest)]}
 
 
 def patches_leg(args, torch, api, wl):
@@ -655,6 +696,7 @@ def headline(result, detail_path):
             h["mesh"]["f64_restrict_mixed_graph_ms"] = _sig(me["f64_restrict_graph_ms_per_step"])
             h["mesh"]["f64_restrict_speedup"] = _sig(me["f64_restrict_speedup_vs_f64_plan_graph"], 3)
             h["mesh"]["f64_restrict_err_e2e"] = _sig(me["f64_restrict_max_rel_err_one_step"], 2)
+            h["mesh"]["f64_restrict_err_arith"] = _sig(me["f64_restrict_kernel_max_rel_err_one_step"], 2)
     if "mesh_patches" in result:
         mp = result["mesh_patches"]
         h["mesh_patches"] = {"f64_plan_graph_ms": _sig(mp["f64_plan_graph"]["ms_per_step"]),
@@ -707,11 +749,13 @@ def main():
     orient_np = batch.orientation.cpu().numpy()
     sub_np = batch.subface.cpu().numpy()
 
-    def make_launches(dtype, mode=None, batch=batch):
+    def make_launches(dtype, mode=None, batch=batch, restrict_mode=None):
+        # restrict_mode FT_F64_TO_F32: restriction reads the float64 fine data
+        # and writes float32 coarse faces; the rest is stored in `dtype`.
         coarse_in = batch.coarse.to(dtype)
-        fine_in = batch.fine.to(dtype)
+        fine_in = batch.fine if restrict_mode == api.FT_F64_TO_F32 else batch.fine.to(dtype)
         coarse_out = coarse_in.clone()
-        fine_out = fine_in.clone()
+        fine_out = batch.fine.to(dtype).clone()
         launches, ops = [], {}
         for scheme in (1, 2, 3):
             rop = api.build_transfer_operator(api.FT_RESTRICT, scheme, p, k)
@@ -721,7 +765,8 @@ def main():
 
             def r(rop=rop):
                 api.restrict_faces(rop, batch.orientation, batch.subface, batch.coarse_offset,
-                                   batch.fine_offset, U, fine_in, coarse_out, mode=mode)
+                                   batch.fine_offset, U, fine_in, coarse_out,
+                                   mode=mode if restrict_mode is None else restrict_mode)
 
             def i(iop=iop):
                 api.interpolate_faces(iop, batch.orientation, batch.subface, batch.coarse_offset,
@@ -801,12 +846,18 @@ def main():
         result["mixed"] = {"workload": "hanging faces p=9 k=3 U=59, unknown u scaled by 10^(-6+9u/58); "
                                        "float32 storage, same step as the FP64 headline; errors of "
                                        "Taylor-3 outputs per unknown"}
-        for label, mode in (("f32", api.FT_F32), ("bf16x3", api.FT_F32_BF16X3), ("bf16x6", api.FT_F32_BF16X6)):
-            mlaunches, mops, mouts = make_launches(torch.float32, mode, b3)
+        # f64_restrict_bf16x6: float64 fine data read by restriction, which
+        # writes float32 coarse faces (one rounding of the FP64 result);
+        # interpolation in six split terms into float32 fine halos.
+        for label, mode, rmode in (("f32", api.FT_F32, None), ("bf16x3", api.FT_F32_BF16X3, None),
+                                   ("bf16x6", api.FT_F32_BF16X6, None),
+                                   ("f64_restrict_bf16x6", api.FT_F32_BF16X6, api.FT_F64_TO_F32)):
+            mlaunches, mops, mouts = make_launches(torch.float32, mode, b3, restrict_mode=rmode)
             mms, mkern = run_steps(mlaunches, args.steps, args.warmup, torch)
             errs, kerrs = {}, {}
             for nm, got, ref, rref in (("interpolate_taylor3", mouts[1], ref_f, rref_f),
-                                       ("restrict_taylor3", mouts[0], ref_c, rref_c)):
+                                       ("restrict_taylor3", mouts[0], ref_c,
+                                        ref_c if rmode is not None else rref_c)):
                 errs[nm] = rel_errors(got, ref)
                 kerrs[nm] = rel_errors(got, rref)
             progress(f"float32 {label} step: {mms:.3f} ms")

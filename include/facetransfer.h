@@ -117,11 +117,22 @@ extern "C" {
  * FT_F32_BF16X6: as FT_F32_BF16X3 plus the compensating products
  *                W0 x2 + W1 x1 + W2 x0 of the split residuals (dropped terms
  *                <= 3 * 2^-24 of sum |w x|, i.e. float32 rounding level).
- *                Restriction as FT_F32. */
+ *                Restriction as FT_F32.
+ * FT_F64_TO_F32: restriction only, face buffers only: float64 fine data,
+ *                float64 sums, float32 coarse faces (each output is the
+ *                FT_F64 result rounded once to float32).  Restriction's
+ *                extrapolation rows (weights of 1-norm up to about 400)
+ *                amplify the rounding of float32-stored fine data to about
+ *                1e-5 of the field; with float64 fine data the coarse faces
+ *                carry only their own float32 rounding, and interpolation
+ *                from them in FT_F32 or FT_F32_BF16X6 into float32 fine halo
+ *                buffers keeps a restrict-then-interpolate step within about
+ *                1e-6 of float64. */
 #define FT_F64 0
 #define FT_F32 1
 #define FT_F32_BF16X3 2
 #define FT_F32_BF16X6 3
+#define FT_F64_TO_F32 4
 
 /* Build flags. */
 #define FT_BUILD_HOST_ONLY 1 /* build the weight tables on the host only; the
@@ -191,7 +202,8 @@ int interpolate_faces(const ft_operator* op, int64_t n_faces, const int8_t* orie
  * coarse centre: injection where they coincide, extrapolation elsewhere).
  * Arguments as for interpolate_faces, with `fine` read only and `coarse`
  * written: per face, the (p/3)^2 * k cells of the coarse face's fine-side half
- * that lie under the subface. */
+ * that lie under the subface.  dtype may also be FT_F64_TO_F32: `fine` then
+ * holds float64 (fine_elems of them) and `coarse` float32. */
 int restrict_faces(const ft_operator* op, int64_t n_faces, const int8_t* orientation,
                    const int8_t* subface, const int64_t* coarse_offset,
                    const int64_t* fine_offset, int unknowns, int dtype, const void* fine,
@@ -343,7 +355,8 @@ typedef struct ft_plan_batch {
  * operators, device arrays and buffers must stay valid while the plan or a
  * graph captured from it is used).
  * dtype as for interpolate_faces; restriction batches of the FT_F32_BF16X*
- * types run as FT_F32.  The schedule starts at a default and can be tuned
+ * types run as FT_F32.  FT_F64_TO_F32 (restriction batches only, face
+ * buffers only) takes a float64 `fine` and a float32 `coarse` array.  The schedule starts at a default and can be tuned
  * with transfer_plan_autotune.  Allocates its small device segment tables.
  * Errors: FT_ERR_INVALID (null pointers, n_batches < 1, operators of another
  * device), FT_ERR_UNSUPPORTED (dtype, unknowns), FT_ERR_NOMEM, FT_ERR_HIP. */
@@ -406,6 +419,16 @@ int destroy_transfer_plan(ft_plan* plan);
  * plan is built): it stays valid after the plan's schedule changes and after
  * destroy_transfer_plan, as long as the operators and buffers live. */
 int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out);
+
+/* As transfer_plan_capture for a step made of several plans: each of the
+ * `steps` captured steps runs plans[0], ..., plans[n_plans - 1] in order
+ * (for instance an FT_F64_TO_F32 restriction plan and then a float32
+ * interpolation plan that reads its coarse faces).  The plans array is
+ * read during the call only; all plans must belong to the current device.
+ * The graph holds every plan's segment tables.
+ * Errors: FT_ERR_INVALID (NULL pointers, n_plans < 1, steps < 1, plans of
+ * another device), FT_ERR_NOMEM, FT_ERR_HIP. */
+int transfer_plans_capture(const ft_plan* const* plans, int n_plans, int steps, ft_graph** out);
 
 /* Launch a captured graph on `stream`. */
 int transfer_graph_launch(const ft_graph* graph, void* stream);

@@ -94,6 +94,8 @@ SIGNATURES = {
         ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int, c_int64_p, ctypes.POINTER(ctypes.c_double)]),
     "destroy_transfer_plan": (ctypes.c_int, [c_void_p]),
     "transfer_plan_capture": (ctypes.c_int, [c_void_p, ctypes.c_int, ctypes.POINTER(c_void_p)]),
+    "transfer_plans_capture": (
+        ctypes.c_int, [ctypes.POINTER(c_void_p), ctypes.c_int, ctypes.c_int, ctypes.POINTER(c_void_p)]),
     "transfer_graph_launch": (ctypes.c_int, [c_void_p, c_void_p]),
     "destroy_transfer_graph": (ctypes.c_int, [c_void_p]),
     "transfer_last_error": (ctypes.c_char_p, []),

@@ -15,7 +15,7 @@ from . import _lib
 FT_OK, FT_ERR_INVALID, FT_ERR_UNSUPPORTED, FT_ERR_HIP, FT_ERR_NOMEM = 0, 1, 2, 3, 4
 FT_INTERPOLATE, FT_RESTRICT = 0, 1
 FT_DLINEAR, FT_TAYLOR2, FT_TAYLOR3 = 1, 2, 3
-FT_F64, FT_F32, FT_F32_BF16X3, FT_F32_BF16X6 = 0, 1, 2, 3
+FT_F64, FT_F32, FT_F32_BF16X3, FT_F32_BF16X6, FT_F64_TO_F32 = 0, 1, 2, 3, 4
 FT_BUILD_HOST_ONLY = 1
 FT_BUILD_2D = 2
 FT_HALF_INNER, FT_HALF_OUTER, FT_HALF_BOTH = 1, 2, 3
@@ -134,18 +134,24 @@ def _descriptors(orientation, subface, coarse_offset, fine_offset):
     return n
 
 
-def _mode(a, b, mode):
-    """The C dtype code for tensors a, b: float64 -> FT_F64; float32 ->
-    FT_F32 unless a split-bfloat16 mode is requested."""
-    _on_device("source buffer", a)
-    _on_device("destination buffer", b)
-    if a.dtype != b.dtype or a.dtype not in _DTYPES:
+def _mode(coarse, fine, mode):
+    """The C dtype code for the coarse and fine tensors: float64 -> FT_F64;
+    float32 -> FT_F32 unless a split-bfloat16 mode is requested;
+    FT_F64_TO_F32 (restriction) only on request, with float64 fine and
+    float32 coarse data."""
+    _on_device("coarse buffer", coarse)
+    _on_device("fine buffer", fine)
+    if mode == FT_F64_TO_F32:
+        if fine.dtype != torch.float64 or coarse.dtype != torch.float32:
+            raise TypeError("FT_F64_TO_F32 takes a float64 fine and a float32 coarse buffer")
+        return mode
+    if coarse.dtype != fine.dtype or coarse.dtype not in _DTYPES:
         raise TypeError("coarse and fine must share dtype float64 or float32")
     if mode is None:
-        return _DTYPES[a.dtype]
-    if a.dtype == torch.float64 and mode != FT_F64:
+        return _DTYPES[coarse.dtype]
+    if coarse.dtype == torch.float64 and mode != FT_F64:
         raise TypeError("float64 buffers only support FT_F64")
-    if a.dtype == torch.float32 and mode not in (FT_F32, FT_F32_BF16X3, FT_F32_BF16X6):
+    if coarse.dtype == torch.float32 and mode not in (FT_F32, FT_F32_BF16X3, FT_F32_BF16X6):
         raise TypeError("float32 buffers support FT_F32, FT_F32_BF16X3 and FT_F32_BF16X6")
     return mode
 
@@ -168,9 +174,10 @@ def interpolate_faces(op, orientation, subface, coarse_offset, fine_offset, unkn
 
 def restrict_faces(op, orientation, subface, coarse_offset, fine_offset, unknowns, fine, coarse,
                    stream=None, mode=None):
-    """Fill each fine face's segment of its coarse face's fine-side half."""
+    """Fill each fine face's segment of its coarse face's fine-side half.
+    mode=FT_F64_TO_F32 restricts float64 fine data into float32 coarse faces."""
     n = _descriptors(orientation, subface, coarse_offset, fine_offset)
-    dt = _mode(fine, coarse, mode)
+    dt = _mode(coarse, fine, mode)
     _check(
         _lib.load().restrict_faces(
             op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
@@ -200,7 +207,7 @@ def restrict_patches(op, orientation, subface, coarse_offset, fine_offset, unkno
                      stream=None, mode=None):
     """Fill, in each coarse patch's halo, the segment under each fine patch."""
     n = _descriptors(orientation, subface, coarse_offset, fine_offset)
-    dt = _mode(fine, coarse, mode)
+    dt = _mode(coarse, fine, mode)
     _check(
         _lib.load().restrict_patches(
             op.handle, n, _ptr(orientation), _ptr(subface), _ptr(coarse_offset), _ptr(fine_offset),
@@ -421,6 +428,15 @@ def transfer_plan_capture(plan, steps=1):
     h = ctypes.c_void_p()
     _check(_lib.load().transfer_plan_capture(plan.handle, steps, ctypes.byref(h)), "transfer_plan_capture")
     return TransferGraph(h.value, plan)
+
+
+def transfer_plans_capture(plans, steps=1):
+    """One graph of `steps` steps, each running the plans in order."""
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    h = ctypes.c_void_p()
+    _check(_lib.load().transfer_plans_capture(arr, len(plans), steps, ctypes.byref(h)),
+           "transfer_plans_capture")
+    return TransferGraph(h.value, list(plans))
 
 
 def transfer_graph_launch(graph, stream=None):

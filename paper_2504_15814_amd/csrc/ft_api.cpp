@@ -172,7 +172,11 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
   if (!op->on_device) return fail(FT_ERR_INVALID, "operator was built host-only");
   if (n_faces < 0) return fail(FT_ERR_INVALID, "n_faces < 0");
   if (unknowns < 1 || unknowns > 4096) return fail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
-  if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return fail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (dtype < FT_F64 || dtype > FT_F64_TO_F32) return fail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (dtype == FT_F64_TO_F32 && direction == FT_INTERPOLATE)
+    return fail(FT_ERR_UNSUPPORTED, "FT_F64_TO_F32 is a restriction type");
+  if (dtype == FT_F64_TO_F32 && patches)
+    return fail(FT_ERR_UNSUPPORTED, "FT_F64_TO_F32 takes face buffers");
   if (direction == FT_INTERPOLATE && (dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6) &&
       op->on_device && !op->d_wbf16)
     return fail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
@@ -188,7 +192,9 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != op->device) return fail(FT_ERR_INVALID, "operator belongs to another device");
-  const int64_t esz = dtype == FT_F64 ? 8 : 4;
+  // FT_F64_TO_F32 (restriction only): float64 source, float32 destination.
+  const int64_t src_size = (dtype == FT_F64 || dtype == FT_F64_TO_F32) ? 8 : 4;
+  const int64_t dst_size = dtype == FT_F64 ? 8 : 4;
   const struct {
     const void* ptr;
     int64_t bytes;
@@ -197,8 +203,8 @@ int check_apply(const ft_operator* op, int direction, int64_t n_faces, const voi
                  {subface, n_faces, "subface"},
                  {so, 8 * n_faces, "source offsets"},
                  {dof, 8 * n_faces, "destination offsets"},
-                 {src, esz * src_elems, "source buffer"},
-                 {dst, esz * dst_elems, "destination buffer"}};
+                 {src, src_size * src_elems, "source buffer"},
+                 {dst, dst_size * dst_elems, "destination buffer"}};
   for (const auto& r : ranges) {
     const std::string err = ft::device_range_error(r.ptr, r.bytes, dev, r.what);
     if (!err.empty()) return fail(FT_ERR_INVALID, err);

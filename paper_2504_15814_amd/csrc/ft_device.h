@@ -188,15 +188,18 @@ __device__ __forceinline__ constexpr int store_row(const int i) {
 // DIR 0: interpolation (src = coarse, dst = fine).  DIR 1: restriction
 // (src = fine, dst = coarse).  R rows per anchor; EC anchors per axis (0 = read
 // from the operator); COPY is the exact-copy row (its source is stencil entry
-// 0 of every block) or -1.  T storage, A accumulator, W weight type.
+// 0 of every block) or -1.  T source storage, A accumulator, W weight type,
+// TD destination storage (float32 for restriction of float64 fine data into
+// float32 coarse faces, else T).
 // DIM 3, or 2 for two-dimensional faces (2k x p cells; no third axis, the
 // anchor index e runs over the p/3 coarse columns of the subface).
-template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W, int DIM = 3>
+template <int DIR, int R, int EC, int COPY, typename T, typename A, typename W, int DIM = 3,
+          typename TD = T>
 __device__ __forceinline__ void apply_item(
     const DevOp* __restrict__ op_, const int face, const int e, const int layout,
     const int8_t* __restrict__ orientation_, const int8_t* __restrict__ subface_,
     const int64_t* __restrict__ src_offset_, const int64_t* __restrict__ dst_offset_, const int U,
-    const T* __restrict__ src, const int64_t src_elems, T* __restrict__ dst,
+    const T* __restrict__ src, const int64_t src_elems, TD* __restrict__ dst,
     const int64_t dst_elems, const W* __restrict__ weights_, int* __restrict__ errors) {
   const FT_CONST DevOp* op = cptr(op_);
   const FT_CONST int8_t* orientation = cptr(orientation_);
@@ -219,7 +222,7 @@ __device__ __forceinline__ void apply_item(
   const int dst_b = g.dst_b, dst_c = g.dst_c;
 
   const T* __restrict__ sp = src + g.so;
-  T* __restrict__ dp = dst + g.dof;
+  TD* __restrict__ dp = dst + g.dof;
   const FT_CONST int* pts = cptr(op->stencil) + g.start;
   const FT_CONST W* wts = weights + (int64_t)g.start * R;
 
@@ -276,7 +279,7 @@ __device__ __forceinline__ void apply_item(
         if (decltype(check)::value && !mine) continue;
         // Streaming (non-temporal) stores: the written halo is not re-read by
         // this launch.
-        __builtin_nontemporal_store(T(r == COPY ? copy_val : acc[r]), &dp[(int64_t)dcell * U + u]);
+        __builtin_nontemporal_store(TD(r == COPY ? copy_val : acc[r]), &dp[(int64_t)dcell * U + u]);
       }
     };
     if (DIR == 0 && DIM == 3 && g.axis == 0) {
@@ -331,13 +334,14 @@ __device__ __forceinline__ void stage_lds(A* __restrict__ to, const int n, const
 // Then lanes run over (row, unknown) outputs and each sums its row over the
 // stencil in stencil order: the same fused multiply-add chain as
 // apply_item, so both bodies give bitwise equal results.  The slice holds
-// width * (R + U) values of A.
-template <int DIR, int R, int COPY, typename T, typename A, typename W, int DIM = 3>
+// width * (R + U) values of A.  Types as for apply_item.
+template <int DIR, int R, int COPY, typename T, typename A, typename W, int DIM = 3,
+          typename TD = T>
 __device__ __forceinline__ void small_item(
     const DevOp* __restrict__ op_, const int face, const int e, const int layout,
     const int8_t* __restrict__ orientation_, const int8_t* __restrict__ subface_,
     const int64_t* __restrict__ src_offset_, const int64_t* __restrict__ dst_offset_, const int U,
-    const T* __restrict__ src, const int64_t src_elems, T* __restrict__ dst,
+    const T* __restrict__ src, const int64_t src_elems, TD* __restrict__ dst,
     const int64_t dst_elems, const W* __restrict__ weights, int* __restrict__ errors,
     A* __restrict__ slice) {
   const FT_CONST DevOp* op = cptr(op_);
@@ -349,7 +353,7 @@ __device__ __forceinline__ void small_item(
                                   errors, &g))
     return;
   const T* __restrict__ sp = src + g.so;
-  T* __restrict__ dp = dst + g.dof;
+  TD* __restrict__ dp = dst + g.dof;
   const int* __restrict__ pts = op_->stencil + g.start;
   const W* __restrict__ wts = weights + (int64_t)g.start * R;
   const int width = g.width;
@@ -376,7 +380,7 @@ __device__ __forceinline__ void small_item(
     } else {
       for (int q = 0; q < width; ++q) acc = fma(ws[q * R + r], xs[q * U + u], acc);
     }
-    if (mine) __builtin_nontemporal_store(T(acc), &dp[(int64_t)dcell * U + u]);
+    if (mine) __builtin_nontemporal_store(TD(acc), &dp[(int64_t)dcell * U + u]);
   }
 }
 

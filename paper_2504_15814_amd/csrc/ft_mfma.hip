@@ -11,9 +11,10 @@
 
 namespace ft {
 
-// Six waves per SIMD: the accumulators then live in 80 VGPRs without spills
-// (the compiler's own choice, 58 VGPRs + 32 AGPRs, allows five; six-term
-// Taylor-3 interpolation 2-3 % faster, same-box A/B).
+// Six waves per SIMD: the accumulators then live in 80 VGPRs (the compiler's
+// own choice, 58 VGPRs + 32 AGPRs, allows five; six-term Taylor-3
+// interpolation 2-3 % faster, same-box A/B).  The six-term form spills three
+// registers under this hint; five waves per SIMD avoids that and is no faster.
 template <int R, int EC, int TERMS, int DIM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void interp_mfma_kernel(
     const DevOp* __restrict__ op, const int64_t n_faces, const int waves_per_block,

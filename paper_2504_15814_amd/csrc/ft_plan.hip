@@ -49,11 +49,13 @@ struct PlanSeg {
   int pad_;
 };
 
-// One work item of a plan segment, for one kind of operator.
-template <typename T, int MODE, int KIND>
+// One work item of a plan segment, for one kind of operator.  T: coarse
+// storage, TF: fine storage (float64 fine data restricted into float32 coarse
+// faces, else T; interpolation only runs with TF = T).
+template <typename T, int MODE, int KIND, typename TF>
 __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const int face_, const int e_,
                                        const int U, T* __restrict__ coarse,
-                                       const int64_t coarse_elems, T* __restrict__ fine,
+                                       const int64_t coarse_elems, TF* __restrict__ fine,
                                        const int64_t fine_elems) {
   const int face = __builtin_amdgcn_readfirstlane(face_);
   const int e = __builtin_amdgcn_readfirstlane(e_);
@@ -62,7 +64,9 @@ __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const i
   if constexpr (KIND == kInterp9 || KIND == kInterp18 || KIND == kInterp27) {
     constexpr int R = KIND == kInterp9 ? 9 : (KIND == kInterp18 ? 18 : 27);
     constexpr int COPY = R >= 18 ? 13 : -1;
-    if constexpr (MODE == 0)
+    if constexpr (!std::is_same_v<T, TF>)
+      return;  // the host admits no interpolation batch into such a plan
+    else if constexpr (MODE == 0)
       apply_item<0, R, 0, COPY, T, T, T>(
           op, face, e, S->layout, S->orientation, S->subface, S->coarse_offset,
           S->fine_offset, U, coarse, coarse_elems, fine, fine_elems,
@@ -76,22 +80,22 @@ __device__ __forceinline__ void plan_item(const PlanSeg* __restrict__ S, const i
                           ? 1
                           : ((KIND == kRestrict2Inject || KIND == kRestrict2Plain) ? 2 : 3);
     constexpr int COPY = (KIND == kRestrict2Inject || KIND == kRestrict3Inject) ? 0 : -1;
-    apply_item<1, R, 0, COPY, T, double, double>(op, face, e, S->layout, S->orientation,
-                                                 S->subface, S->fine_offset, S->coarse_offset,
-                                                 U, fine, fine_elems, coarse, coarse_elems,
-                                                 cop->w64, S->errors);
+    apply_item<1, R, 0, COPY, TF, double, double, 3, T>(op, face, e, S->layout, S->orientation,
+                                                        S->subface, S->fine_offset,
+                                                        S->coarse_offset, U, fine, fine_elems,
+                                                        coarse, coarse_elems, cop->w64, S->errors);
   }
 }
 
 // MODE 0: interpolation on the vector ALUs in precision T; MODE 3 / 6:
 // float32 interpolation on the matrix cores with that many bfloat16 product
-// terms.  Restriction always sums in float64.
-template <typename T, int MODE>
+// terms.  Restriction always sums in float64.  Storage types as for plan_item.
+template <typename T, int MODE, typename TF = T>
 __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ segs,
                                                    const int nseg, const int wpb,
                                                    const int remap, const int U,
                                                    T* __restrict__ coarse, const int64_t coarse_elems,
-                                                   T* __restrict__ fine, const int64_t fine_elems) {
+                                                   TF* __restrict__ fine, const int64_t fine_elems) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int64_t b = blockIdx.x;
   if (remap) {
@@ -116,8 +120,8 @@ __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ s
   for (int64_t it = first; it < item_end; it += stride) {                                      \
     const int local = (int)(it - item0); /* segments hold < 2^31 items */                      \
     const int face = local / anchors;                                                          \
-    plan_item<T, MODE, KIND>(S, face, local - face * anchors, U, coarse, coarse_elems, fine,   \
-                             fine_elems);                                                      \
+    plan_item<T, MODE, KIND, TF>(S, face, local - face * anchors, U, coarse, coarse_elems,     \
+                                 fine, fine_elems);                                            \
   }                                                                                            \
   break;
       case kInterp18: FT_PLAN_LOOP(kInterp18)
@@ -137,13 +141,13 @@ __global__ __launch_bounds__(256) void plan_kernel(const PlanSeg* __restrict__ s
 // item once, and each wave finds its segment by binary search over the
 // segment table (a handful of scalar loads).  Without the grid-stride loop
 // the bodies keep their stand-alone register budget.
-template <typename T, int MODE>
+template <typename T, int MODE, typename TF = T>
 __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restrict__ segs,
                                                         const int nseg, const int64_t total,
                                                         const int wpb, const int remap,
                                                         const int U, T* __restrict__ coarse,
                                                         const int64_t coarse_elems,
-                                                        T* __restrict__ fine,
+                                                        TF* __restrict__ fine,
                                                         const int64_t fine_elems) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int64_t b = blockIdx.x;
@@ -166,23 +170,24 @@ __global__ __launch_bounds__(256) void plan_item_kernel(const PlanSeg* __restric
   const int face = local / anchors;
   const int e = local - face * anchors;
   switch (S->kind) {
-    case kInterp18: plan_item<T, MODE, kInterp18>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kInterp27: plan_item<T, MODE, kInterp27>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict2Inject: plan_item<T, MODE, kRestrict2Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict2Plain: plan_item<T, MODE, kRestrict2Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict3Inject: plan_item<T, MODE, kRestrict3Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kInterp9: plan_item<T, MODE, kInterp9>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
-    case kRestrict1Plain: plan_item<T, MODE, kRestrict1Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
-    default: plan_item<T, MODE, kRestrict3Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp18: plan_item<T, MODE, kInterp18, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp27: plan_item<T, MODE, kInterp27, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict2Inject: plan_item<T, MODE, kRestrict2Inject, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict2Plain: plan_item<T, MODE, kRestrict2Plain, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict3Inject: plan_item<T, MODE, kRestrict3Inject, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kInterp9: plan_item<T, MODE, kInterp9, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    case kRestrict1Plain: plan_item<T, MODE, kRestrict1Plain, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
+    default: plan_item<T, MODE, kRestrict3Plain, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems); break;
   }
 }
 
 // One work item of a plan segment with the small-U body (few unknowns per
 // cell): every mode runs on the vector ALUs, as the per-batch calls do.
-template <typename T, int KIND>
+// Storage types as for plan_item.
+template <typename T, int KIND, typename TF>
 __device__ __forceinline__ void plan_small_item(const PlanSeg* __restrict__ S, const int face_,
                                                 const int e_, const int U, T* __restrict__ coarse,
-                                                const int64_t coarse_elems, T* __restrict__ fine,
+                                                const int64_t coarse_elems, TF* __restrict__ fine,
                                                 const int64_t fine_elems, double* xs_words) {
   const int face = __builtin_amdgcn_readfirstlane(face_);
   const int e = __builtin_amdgcn_readfirstlane(e_);
@@ -191,32 +196,35 @@ __device__ __forceinline__ void plan_small_item(const PlanSeg* __restrict__ S, c
   if constexpr (KIND == kInterp9 || KIND == kInterp18 || KIND == kInterp27) {
     constexpr int R = KIND == kInterp9 ? 9 : (KIND == kInterp18 ? 18 : 27);
     constexpr int COPY = R >= 18 ? 13 : -1;
-    small_item<0, R, COPY, T, T, T>(
-        op, face, e, S->layout, S->orientation, S->subface, S->coarse_offset, S->fine_offset, U,
-        coarse, coarse_elems, fine, fine_elems,
-        (const T*)(sizeof(T) == 8 ? (const void*)cop->w64 : (const void*)cop->w32), S->errors,
-        reinterpret_cast<T*>(xs_words));
+    if constexpr (!std::is_same_v<T, TF>)
+      return;  // the host admits no interpolation batch into such a plan
+    else
+      small_item<0, R, COPY, T, T, T>(
+          op, face, e, S->layout, S->orientation, S->subface, S->coarse_offset, S->fine_offset, U,
+          coarse, coarse_elems, fine, fine_elems,
+          (const T*)(sizeof(T) == 8 ? (const void*)cop->w64 : (const void*)cop->w32), S->errors,
+          reinterpret_cast<T*>(xs_words));
   } else {
     constexpr int R = KIND == kRestrict1Plain
                           ? 1
                           : ((KIND == kRestrict2Inject || KIND == kRestrict2Plain) ? 2 : 3);
     constexpr int COPY = (KIND == kRestrict2Inject || KIND == kRestrict3Inject) ? 0 : -1;
-    small_item<1, R, COPY, T, double, double>(op, face, e, S->layout, S->orientation, S->subface,
-                                              S->fine_offset, S->coarse_offset, U, fine,
-                                              fine_elems, coarse, coarse_elems, cop->w64,
-                                              S->errors, xs_words);
+    small_item<1, R, COPY, TF, double, double, 3, T>(op, face, e, S->layout, S->orientation,
+                                                     S->subface, S->fine_offset, S->coarse_offset,
+                                                     U, fine, fine_elems, coarse, coarse_elems,
+                                                     cop->w64, S->errors, xs_words);
   }
 }
 
 // The non-persistent plan launch with the small-U body; each wave owns
 // xs_stride words of the block's dynamic LDS.
-template <typename T>
+template <typename T, typename TF = T>
 __global__ __launch_bounds__(256) void plan_small_kernel(const PlanSeg* __restrict__ segs,
                                                          const int nseg, const int64_t total,
                                                          const int wpb, const int remap,
                                                          const int U, T* __restrict__ coarse,
                                                          const int64_t coarse_elems,
-                                                         T* __restrict__ fine,
+                                                         TF* __restrict__ fine,
                                                          const int64_t fine_elems,
                                                          const int xs_stride) {
   extern __shared__ double plan_lds[];
@@ -240,14 +248,14 @@ __global__ __launch_bounds__(256) void plan_small_kernel(const PlanSeg* __restri
   const int e = local - face * anchors;
   double* xs = plan_lds + wave * xs_stride;
   switch (S->kind) {
-    case kInterp18: plan_small_item<T, kInterp18>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
-    case kInterp27: plan_small_item<T, kInterp27>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
-    case kRestrict2Inject: plan_small_item<T, kRestrict2Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
-    case kRestrict2Plain: plan_small_item<T, kRestrict2Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
-    case kRestrict3Inject: plan_small_item<T, kRestrict3Inject>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
-    case kInterp9: plan_small_item<T, kInterp9>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
-    case kRestrict1Plain: plan_small_item<T, kRestrict1Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
-    default: plan_small_item<T, kRestrict3Plain>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kInterp18: plan_small_item<T, kInterp18, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kInterp27: plan_small_item<T, kInterp27, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict2Inject: plan_small_item<T, kRestrict2Inject, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict2Plain: plan_small_item<T, kRestrict2Plain, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict3Inject: plan_small_item<T, kRestrict3Inject, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kInterp9: plan_small_item<T, kInterp9, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    case kRestrict1Plain: plan_small_item<T, kRestrict1Plain, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
+    default: plan_small_item<T, kRestrict3Plain, TF>(S, face, e, U, coarse, coarse_elems, fine, fine_elems, xs); break;
   }
 }
 
@@ -312,7 +320,7 @@ struct ft_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int device = -1;
-  std::shared_ptr<ft::PlanTables> tables;  // read by the captured kernels
+  std::vector<std::shared_ptr<ft::PlanTables>> tables;  // read by the captured kernels
 };
 
 namespace {
@@ -355,9 +363,11 @@ int check_batches(const ft_plan_batch* batches, int n_batches, int unknowns, int
                   int flags, int* dev_out) {
   if (!batches || n_batches < 1) return pfail(FT_ERR_INVALID, "need at least one batch");
   if (unknowns < 1 || unknowns > 4096) return pfail(FT_ERR_UNSUPPORTED, "unknowns must be 1..4096");
-  if (dtype < FT_F64 || dtype > FT_F32_BF16X6) return pfail(FT_ERR_UNSUPPORTED, "unsupported dtype");
+  if (dtype < FT_F64 || dtype > FT_F64_TO_F32) return pfail(FT_ERR_UNSUPPORTED, "unsupported dtype");
   if (flags & ~(FT_PLAN_RESTRICT_FIRST | FT_PLAN_PATCHES))
     return pfail(FT_ERR_INVALID, "unknown flags");
+  if (dtype == FT_F64_TO_F32 && (flags & FT_PLAN_PATCHES))
+    return pfail(FT_ERR_UNSUPPORTED, "FT_F64_TO_F32 takes face buffers");
   // Face buffers: one array for coarse and fine would let a face overwrite
   // what it reads.  Patches: reads are face views, writes halos of other
   // faces, so one pool may hold both.
@@ -377,14 +387,18 @@ int check_batches(const ft_plan_batch* batches, int n_batches, int unknowns, int
       return pfail(FT_ERR_INVALID, "batch with NULL descriptor arrays");
     if (b.n_faces * (int64_t)b.op->E * b.op->E >= ((int64_t)1 << 31))
       return pfail(FT_ERR_UNSUPPORTED, "batch too large (faces x anchors must stay below 2^31)");
-    if (dtype >= FT_F32_BF16X3 && b.op->direction == FT_INTERPOLATE && !b.op->d_wbf16)
+    if (dtype == FT_F64_TO_F32 && b.op->direction == FT_INTERPOLATE)
+      return pfail(FT_ERR_UNSUPPORTED, "FT_F64_TO_F32 is a restriction type (interpolation batch)");
+    if ((dtype == FT_F32_BF16X3 || dtype == FT_F32_BF16X6) && b.op->direction == FT_INTERPOLATE &&
+        !b.op->d_wbf16)
       return pfail(FT_ERR_UNSUPPORTED, "operator blocks too wide for the matrix-core path");
   }
   // Every array the kernels will dereference must be device memory of this
   // device, as large as stated.
-  const int64_t esz = dtype == FT_F64 ? 8 : 4;
-  std::string err = ft::device_range_error(coarse, esz * coarse_elems, dev, "coarse buffer");
-  if (err.empty()) err = ft::device_range_error(fine, esz * fine_elems, dev, "fine buffer");
+  const int64_t coarse_size = dtype == FT_F64 ? 8 : 4;
+  const int64_t fine_size = (dtype == FT_F64 || dtype == FT_F64_TO_F32) ? 8 : 4;
+  std::string err = ft::device_range_error(coarse, coarse_size * coarse_elems, dev, "coarse buffer");
+  if (err.empty()) err = ft::device_range_error(fine, fine_size * fine_elems, dev, "fine buffer");
   for (int i = 0; i < n_batches && err.empty(); ++i) {
     const ft_plan_batch& b = batches[i];
     if (b.n_faces == 0) continue;
@@ -433,7 +447,7 @@ int widest_block(const ft_plan_batch* batches, int n_batches) {
 
 // Small-U launch of one phase: one wave per work item (the persistent form
 // and the matrix-core bodies are not used for few unknowns).
-template <typename T>
+template <typename T, typename TF = T>
 hipError_t launch_small_items(const ft::PlanSeg* segs, int nseg, int64_t total, int wpb, int remap,
                               int U, int widest, void* coarse, int64_t coarse_elems, void* fine,
                               int64_t fine_elems, hipStream_t stream) {
@@ -444,10 +458,25 @@ hipError_t launch_small_items(const ft::PlanSeg* segs, int nseg, int64_t total, 
   const int xs_stride = widest * (27 + U);
   const size_t lds = (size_t)wpb * xs_stride * sizeof(double);
   if (lds > 65536) return hipErrorInvalidValue;  // beyond one workgroup's LDS
-  hipLaunchKernelGGL((ft::plan_small_kernel<T>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
+  hipLaunchKernelGGL((ft::plan_small_kernel<T, TF>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
                      stream, segs, nseg, total, wpb, remap, U, static_cast<T*>(coarse),
-                     coarse_elems, static_cast<T*>(fine), fine_elems, xs_stride);
+                     coarse_elems, static_cast<TF*>(fine), fine_elems, xs_stride);
   return hipGetLastError();
+}
+
+// The small-U launch for a plan's storage types.
+hipError_t launch_small_typed(int dtype, const ft::PlanSeg* segs, int nseg, int64_t total,
+                              int wpb, int remap, int U, int widest, void* coarse,
+                              int64_t coarse_elems, void* fine, int64_t fine_elems,
+                              hipStream_t stream) {
+  if (dtype == FT_F64)
+    return launch_small_items<double>(segs, nseg, total, wpb, remap, U, widest, coarse,
+                                      coarse_elems, fine, fine_elems, stream);
+  if (dtype == FT_F64_TO_F32)
+    return launch_small_items<float, double>(segs, nseg, total, wpb, remap, U, widest, coarse,
+                                             coarse_elems, fine, fine_elems, stream);
+  return launch_small_items<float>(segs, nseg, total, wpb, remap, U, widest, coarse,
+                                   coarse_elems, fine, fine_elems, stream);
 }
 
 // Build and upload the segment tables of both phases in both orders.
@@ -494,25 +523,25 @@ int upload_tables(ft_plan* plan) {
   return FT_OK;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, typename TF = T>
 hipError_t launch_phase(const ft_plan* plan, int ph, hipStream_t stream) {
   const int wpb = wpb_of(plan->schedule);
   const int64_t want = (plan->total[ph] + wpb - 1) / wpb;
   if (!persistent_of(plan->schedule)) {
     if (want > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((ft::plan_item_kernel<T, MODE>), dim3((unsigned)want), dim3(64 * wpb), 0,
-                       stream, plan->tables->d_segs[ph][heavy_of(plan->schedule)],
+    hipLaunchKernelGGL((ft::plan_item_kernel<T, MODE, TF>), dim3((unsigned)want), dim3(64 * wpb),
+                       0, stream, plan->tables->d_segs[ph][heavy_of(plan->schedule)],
                        plan->nseg[ph], plan->total[ph], wpb,
                        remap_of(plan->schedule), plan->U, static_cast<T*>(plan->coarse),
-                       plan->coarse_elems, static_cast<T*>(plan->fine), plan->fine_elems);
+                       plan->coarse_elems, static_cast<TF*>(plan->fine), plan->fine_elems);
     return hipGetLastError();
   }
   const int64_t blocks = std::min<int64_t>(want, (int64_t)plan->n_cu * bpc_of(plan->schedule));
-  hipLaunchKernelGGL((ft::plan_kernel<T, MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0, stream,
-                     plan->tables->d_segs[ph][heavy_of(plan->schedule)], plan->nseg[ph], wpb,
-                     remap_of(plan->schedule), plan->U,
+  hipLaunchKernelGGL((ft::plan_kernel<T, MODE, TF>), dim3((unsigned)blocks), dim3(64 * wpb), 0,
+                     stream, plan->tables->d_segs[ph][heavy_of(plan->schedule)], plan->nseg[ph],
+                     wpb, remap_of(plan->schedule), plan->U,
                      static_cast<T*>(plan->coarse), plan->coarse_elems,
-                     static_cast<T*>(plan->fine), plan->fine_elems);
+                     static_cast<TF*>(plan->fine), plan->fine_elems);
   return hipGetLastError();
 }
 
@@ -522,23 +551,21 @@ int run_plan(const ft_plan* plan, hipStream_t stream) {
     // Restriction items run the same vector-ALU body in every float32 mode; a
     // phase without interpolation takes the kernel without matrix-core code
     // (fewer registers, more waves per SIMD).
-    const int dtype = (plan->dtype != FT_F64 && !plan->interp[ph]) ? FT_F32 : plan->dtype;
+    const int dtype = (plan->dtype != FT_F64 && plan->dtype != FT_F64_TO_F32 && !plan->interp[ph])
+                          ? FT_F32
+                          : plan->dtype;
     hipError_t e;
     if (plan->U <= ft::LaunchConfig().small_unknowns[0]) {
-      const ft::PlanSeg* segs = plan->tables->d_segs[ph][heavy_of(plan->schedule)];
-      const int wpb = wpb_of(plan->schedule), remap = remap_of(plan->schedule);
-      e = plan->dtype == FT_F64
-              ? launch_small_items<double>(segs, plan->nseg[ph], plan->total[ph], wpb, remap, plan->U,
-                                           plan->widest, plan->coarse, plan->coarse_elems,
-                                           plan->fine, plan->fine_elems, stream)
-              : launch_small_items<float>(segs, plan->nseg[ph], plan->total[ph], wpb, remap, plan->U,
-                                          plan->widest, plan->coarse, plan->coarse_elems,
-                                          plan->fine, plan->fine_elems, stream);
+      e = launch_small_typed(plan->dtype, plan->tables->d_segs[ph][heavy_of(plan->schedule)],
+                             plan->nseg[ph], plan->total[ph], wpb_of(plan->schedule),
+                             remap_of(plan->schedule), plan->U, plan->widest, plan->coarse,
+                             plan->coarse_elems, plan->fine, plan->fine_elems, stream);
       if (e != hipSuccess) return phip(e, "run_transfer_plan launch");
       continue;
     }
     switch (dtype) {
       case FT_F64: e = launch_phase<double, 0>(plan, ph, stream); break;
+      case FT_F64_TO_F32: e = launch_phase<float, 0, double>(plan, ph, stream); break;
       case FT_F32: e = launch_phase<float, 0>(plan, ph, stream); break;
       case FT_F32_BF16X3: e = launch_phase<float, 3>(plan, ph, stream); break;
       default: e = launch_phase<float, 6>(plan, ph, stream); break;
@@ -570,15 +597,15 @@ int scratch_on(int dev, ft::PlanSeg** out) {
 
 // One wave per work item, four waves per block, over `nseg` segments at
 // `segs` (the default plan schedule).
-template <typename T, int MODE>
+template <typename T, int MODE, typename TF = T>
 hipError_t launch_items(const ft::PlanSeg* segs, int nseg, int64_t total, int U, void* coarse,
                         int64_t coarse_elems, void* fine, int64_t fine_elems, hipStream_t stream) {
   constexpr int wpb = 4;
   const int64_t blocks = (total + wpb - 1) / wpb;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((ft::plan_item_kernel<T, MODE>), dim3((unsigned)blocks), dim3(64 * wpb), 0,
-                     stream, segs, nseg, total, wpb, 0, U, static_cast<T*>(coarse), coarse_elems,
-                     static_cast<T*>(fine), fine_elems);
+  hipLaunchKernelGGL((ft::plan_item_kernel<T, MODE, TF>), dim3((unsigned)blocks), dim3(64 * wpb),
+                     0, stream, segs, nseg, total, wpb, 0, U, static_cast<T*>(coarse),
+                     coarse_elems, static_cast<TF*>(fine), fine_elems);
   return hipGetLastError();
 }
 
@@ -666,18 +693,17 @@ int run_transfer_batches(const ft_plan_batch* batches, int n_batches, int unknow
     }
     if (e != hipSuccess) return phip(e, "run_transfer_batches table fill");
     if (unknowns <= ft::LaunchConfig().small_unknowns[0]) {
-      const int widest = widest_block(batches, n_batches);
-      e = dtype == FT_F64 ? launch_small_items<double>(segs, count[ph], item, 4, 0, unknowns, widest,
-                                                       coarse, coarse_elems, fine, fine_elems, s)
-                          : launch_small_items<float>(segs, count[ph], item, 4, 0, unknowns, widest,
-                                                      coarse, coarse_elems, fine, fine_elems, s);
+      e = launch_small_typed(dtype, segs, count[ph], item, 4, 0, unknowns,
+                             widest_block(batches, n_batches), coarse, coarse_elems, fine,
+                             fine_elems, s);
       if (e != hipSuccess) return phip(e, "run_transfer_batches launch");
       continue;
     }
     // As in plans: a phase without interpolation runs the vector-ALU kernel.
-    const int mode = (dtype != FT_F64 && !interp) ? FT_F32 : dtype;
+    const int mode = (dtype != FT_F64 && dtype != FT_F64_TO_F32 && !interp) ? FT_F32 : dtype;
     switch (mode) {
       case FT_F64: e = launch_items<double, 0>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
+      case FT_F64_TO_F32: e = launch_items<float, 0, double>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
       case FT_F32: e = launch_items<float, 0>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
       case FT_F32_BF16X3: e = launch_items<float, 3>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
       default: e = launch_items<float, 6>(segs, count[ph], item, unknowns, coarse, coarse_elems, fine, fine_elems, s); break;
@@ -775,14 +801,22 @@ int destroy_transfer_plan(ft_plan* plan) {
   return FT_OK;
 }
 
-int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out) {
+int transfer_plans_capture(const ft_plan* const* plans, int n_plans, int steps, ft_graph** out) {
   if (!out) return pfail(FT_ERR_INVALID, "out is NULL");
   *out = nullptr;
-  if (!plan || steps < 1) return pfail(FT_ERR_INVALID, "NULL plan or steps < 1");
+  if (!plans || n_plans < 1 || steps < 1)
+    return pfail(FT_ERR_INVALID, "NULL plans, n_plans < 1 or steps < 1");
+  int dev = -1;
+  const hipError_t de = hipGetDevice(&dev);
+  if (de != hipSuccess) return phip(de, "hipGetDevice");
+  for (int i = 0; i < n_plans; ++i) {
+    if (!plans[i]) return pfail(FT_ERR_INVALID, "NULL plan");
+    if (plans[i]->device != dev) return pfail(FT_ERR_INVALID, "plan belongs to another device");
+  }
   ft_graph* g = new (std::nothrow) ft_graph();
   if (!g) return pfail(FT_ERR_NOMEM, "host allocation failed");
-  g->device = plan->device;
-  g->tables = plan->tables;
+  g->device = dev;
+  for (int i = 0; i < n_plans; ++i) g->tables.push_back(plans[i]->tables);
   hipError_t e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete g;
@@ -791,7 +825,8 @@ int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out) {
   int rc = FT_OK;
   e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) rc = phip(e, "hipStreamBeginCapture");
-  for (int i = 0; i < steps && rc == FT_OK; ++i) rc = run_plan(plan, g->stream);
+  for (int i = 0; i < steps && rc == FT_OK; ++i)
+    for (int j = 0; j < n_plans && rc == FT_OK; ++j) rc = run_plan(plans[j], g->stream);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(g->stream, &graph);
   if (rc == FT_OK && e != hipSuccess) rc = phip(e, "hipStreamEndCapture");
@@ -807,6 +842,14 @@ int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out) {
   *out = g;
   ft::set_last_error("");
   return FT_OK;
+}
+
+int transfer_plan_capture(const ft_plan* plan, int steps, ft_graph** out) {
+  if (!plan) {
+    if (out) *out = nullptr;
+    return pfail(FT_ERR_INVALID, "NULL plan or steps < 1");
+  }
+  return transfer_plans_capture(&plan, 1, steps, out);
 }
 
 int transfer_graph_launch(const ft_graph* graph, void* stream) {

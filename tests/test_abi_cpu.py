@@ -35,6 +35,13 @@ def test_exports_every_declared_symbol():
     assert set(names) == set(_lib.SIGNATURES)
 
 
+def test_binding_constants_match_the_header():
+    defines = dict(re.findall(r"^#define (FT_\w+) (\d+)", open(HEADER).read(), flags=re.M))
+    assert "FT_F64_TO_F32" in defines and "FT_PLAN_PATCHES" in defines
+    for name, value in defines.items():
+        assert getattr(api, name) == int(value), name
+
+
 def test_version_and_empty_error():
     assert api.transfer_version() == 200
     assert isinstance(api.transfer_last_error(), str)
@@ -167,6 +174,15 @@ def test_plan_checks_happen_on_host():
     assert lib.run_transfer_plan(None, None) == api.FT_ERR_INVALID
     assert lib.transfer_plan_set_schedule(None, 4) == api.FT_ERR_INVALID
     assert lib.transfer_plan_capture(None, 1, ctypes.byref(h)) == api.FT_ERR_INVALID
+    assert lib.transfer_plans_capture(None, 1, 1, ctypes.byref(h)) == api.FT_ERR_INVALID
+    plans = (ctypes.c_void_p * 1)(None)
+    assert lib.transfer_plans_capture(plans, 0, 1, ctypes.byref(h)) == api.FT_ERR_INVALID
+    assert lib.transfer_plans_capture(plans, 1, 0, ctypes.byref(h)) == api.FT_ERR_INVALID
+    # float64 fine into float32 coarse data: face buffers only, checked first
+    assert lib.build_transfer_plan(arr, 1, 59, api.FT_F64_TO_F32, p, 100, ctypes.c_void_p(128), 100,
+                                   api.FT_PLAN_PATCHES, ctypes.byref(h)) == api.FT_ERR_UNSUPPORTED
+    assert lib.build_transfer_plan(arr, 1, 59, api.FT_F64_TO_F32 + 1, p, 100, ctypes.c_void_p(128), 100, 0,
+                                   ctypes.byref(h)) == api.FT_ERR_UNSUPPORTED
     assert lib.transfer_graph_launch(None, None) == api.FT_ERR_INVALID
     assert lib.destroy_transfer_plan(None) == api.FT_OK
     assert lib.destroy_transfer_graph(None) == api.FT_OK
