@@ -208,3 +208,36 @@ def test_mixed_storage_mesh_step(mesh):
         eager(c32, h32, 1)  # eager work between replays
         torch.cuda.synchronize()
     assert rop.errors() == 0 and iop.errors() == 0
+
+
+@pytest.fixture(scope="module")
+def w3_full(dev):
+    return wl.workload3(device=dev)
+
+
+@pytest.mark.parametrize("scheme", [1, 3])
+def test_full_size_precision_workload(w3_full, scheme):
+    """20,000 faces x 59 unknowns scaled 1e-6 .. 1e3, in the benchmark's
+    launch configuration: on the device, for all faces, every written element
+    is written, nothing else changes and every value is the FP64 result
+    rounded to float32; a seeded sample of 150 faces against the oracle."""
+    b = w3_full
+    op = api.build_transfer_operator(api.FT_RESTRICT, scheme, b.p, b.k)
+    got, before, ref = restrict_both(op, b)
+    mask = gh.device_written_mask(1, scheme, b.p, b.k, b.U, b.orientation, b.subface, b.coarse_offset,
+                                  got.numel(), got.device)
+    gh.check_written_region(got, before, mask)
+    assert torch.equal(got[mask], ref[mask].float())
+    del mask, ref
+    rng = np.random.default_rng(400 + scheme)
+    faces = np.sort(rng.choice(b.n, size=150, replace=False))
+    cb = gh.compact_batch(b, faces)
+    g = gh.compact_faces(got, b.coarse_offset, faces, b.face_elems)
+    before_np = gh.compact_faces(before, b.coarse_offset, faces, b.face_elems)
+    want, (o, s, co) = gh.run_oracle(1, scheme, cb, cb.fine.numpy(), before_np)
+    m, copy = gh.written_mask(1, scheme, b.p, b.k, b.U, o, s, co, len(want))
+    w, gm = want[m].reshape(-1, b.U), g[m].reshape(-1, b.U)
+    bound = 2.0**-24 * np.abs(w) + 2e-12 * np.abs(w).max(axis=0)
+    assert (np.abs(gm - w) <= bound).all(), float((np.abs(gm - w) / np.maximum(bound, 1e-300)).max())
+    assert np.array_equal(g[copy], want[copy].astype(np.float32).astype(np.float64))
+    assert np.array_equal(g[~m], before_np[~m])

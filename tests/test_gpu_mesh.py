@@ -186,3 +186,36 @@ def test_full_size_mesh_step(mesh_full):
         for c0 in range(0, ref.numel(), 1 << 27):
             diff = max(diff, float((got[c0:c0 + (1 << 27)].double() - ref[c0:c0 + (1 << 27)]).abs().max()))
         assert diff / scale < 1e-6, diff / scale
+
+
+def test_full_size_mixed_storage_step(mesh_full):
+    """The benchmark's AMR-mesh step with float64 fine data: restriction of
+    the float64 fine faces into float32 coarse faces, then six-term float32
+    interpolation into float32 fine halo buffers, as two plans captured in
+    one graph.  It equals the per-call step bit for bit and stays within
+    1e-6 (relative to the largest value) of the FP64 step end to end."""
+    mf = mesh_full
+    U = mf.U
+    d = (mf.orientation, mf.subface, mf.coarse_offset, mf.fine_offset)
+    rop = api.build_transfer_operator(1, 3, mf.p, mf.k)
+    iop = api.build_transfer_operator(0, 3, mf.p, mf.k)
+    cs, hs = mf.coarse.float(), mf.fine.float()
+    rplan = api.build_transfer_plan([(rop, *d)], U, cs, mf.fine, mode=api.FT_F64_TO_F32)
+    iplan = api.build_transfer_plan([(iop, *d)], U, cs, hs, mode=api.FT_F32_BF16X6)
+    graph = api.transfer_plans_capture([rplan, iplan], steps=1)
+    graph.launch()
+    pc, ph = mf.coarse.float(), mf.fine.float()
+    api.restrict_faces(rop, *d, U, mf.fine, pc, mode=api.FT_F64_TO_F32)
+    api.interpolate_faces(iop, *d, U, pc, ph, mode=api.FT_F32_BF16X6)
+    torch.cuda.synchronize()
+    assert torch.equal(cs, pc) and torch.equal(hs, ph)
+    del pc, ph
+    ec, ef = mf.coarse.clone(), mf.fine.clone()
+    step_eager(mf, rop, iop, ec, ef)
+    torch.cuda.synchronize()
+    assert rop.errors() == 0 and iop.errors() == 0
+    for got, ref in ((cs, ec), (hs, ef)):
+        diff, scale = 0.0, float(ref.abs().max())
+        for c0 in range(0, ref.numel(), 1 << 27):
+            diff = max(diff, float((got[c0:c0 + (1 << 27)].double() - ref[c0:c0 + (1 << 27)]).abs().max()))
+        assert diff / scale <= 1e-6, diff / scale
