@@ -761,25 +761,23 @@ int transfer_plan_autotune(ft_plan* plan, void* stream, int reps, int64_t* best_
       for (int wpb : {2, 4})
         cands.push_back(wpb | (1LL << 8) | ((int64_t)remap << 16) | ((int64_t)heavy << 17));
   for (const int64_t sch : cands) {
-        {
-          if ((rc = transfer_plan_set_schedule(plan, sch)) != FT_OK) break;
-          if ((rc = run_plan(plan, s)) != FT_OK) break;  // warm-up
-          (void)hipEventRecord(e0, s);
-          for (int r = 0; r < reps && rc == FT_OK; ++r) rc = run_plan(plan, s);
-          (void)hipEventRecord(e1, s);
-          if (rc != FT_OK) break;
-          if (hipEventSynchronize(e1) != hipSuccess) {
-            rc = pfail(FT_ERR_HIP, "autotune synchronisation");
-            break;
-          }
-          float ms = 0.0f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          const double t = ms / reps;
-          if (t < best_t) {
-            best_t = t;
-            best = sch;
-          }
-        }
+    if ((rc = transfer_plan_set_schedule(plan, sch)) != FT_OK) break;
+    if ((rc = run_plan(plan, s)) != FT_OK) break;  // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && rc == FT_OK; ++r) rc = run_plan(plan, s);
+    (void)hipEventRecord(e1, s);
+    if (rc != FT_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      rc = pfail(FT_ERR_HIP, "autotune synchronisation");
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double t = ms / reps;
+    if (t < best_t) {
+      best_t = t;
+      best = sch;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
