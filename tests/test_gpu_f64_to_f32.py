@@ -127,11 +127,12 @@ def restriction_mix(dev, U, seed):
     return mb, ops, batches
 
 
-@pytest.mark.parametrize("U", [59, 3])
+@pytest.mark.parametrize("U", [59, 12, 3])
 def test_plan_schedules_and_fused_launch_equal_per_batch_calls(dev, U):
     """A restriction-only plan over the mix: bitwise equal to the per-batch
     calls under every schedule (persistent ones included) and equal to the
-    allocation-free fused launch."""
+    allocation-free fused launch.  At U = 12 the per-batch calls run the
+    few-unknowns body and the plan the one-lane-per-unknown body."""
     mb, ops, batches = restriction_mix(dev, U, seed=902 + U)
     assert len(batches) >= 10
     ref = torch.full(mb.coarse.shape, gh.SENTINEL, dtype=torch.float32, device=dev)
