@@ -46,12 +46,22 @@ __device__ __forceinline__ const FT_CONST P* cptr(const P* p) {
   return (const FT_CONST P*)p;
 }
 
-// Logical block number.  Hardware dispatches block i to XCD i % 8; with
-// xcd_remap each XCD receives a contiguous range of logical blocks instead,
-// so neighbouring anchors of one face share that XCD's L2.
+// Logical block number.  Hardware dispatches block i to XCD i % 8.
+// xcd_remap 1: each XCD receives a contiguous range of logical blocks, so
+// neighbouring anchors of one face share that XCD's L2.  xcd_remap 2: each
+// XCD receives runs of kXcdRun consecutive logical blocks (16 anchors with
+// four waves per block), so the anchors of a face mostly share one L2 while
+// the eight XCDs work on neighbouring faces at any time.
+constexpr int kXcdRun = 4;
 __device__ inline int64_t logical_block(int xcd_remap) {
   const int64_t b = blockIdx.x;
   if (!xcd_remap) return b;
+  if (xcd_remap == 2) {
+    const int64_t full = gridDim.x / (8 * kXcdRun) * (8 * kXcdRun);
+    if (b >= full) return b;
+    const int64_t j = b / 8;  // the j-th block dispatched to XCD b % 8
+    return (j / kXcdRun) * (8 * kXcdRun) + (b % 8) * kXcdRun + j % kXcdRun;
+  }
   const int64_t nb = gridDim.x;
   const int64_t per = nb / 8;
   const int64_t full = per * 8;

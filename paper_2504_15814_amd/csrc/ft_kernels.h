@@ -39,8 +39,8 @@ struct LaunchConfig {
   int waves_per_block = 4;  // 1..4 (1 and 2 are 1-8 % slower)
   // Consecutive blocks on one XCD, so that the anchors of a face share one
   // L2: halves the float64 interpolation's L2 misses (Taylor-3: 1.49 -> 0.75
-  // GB per 20,000 faces) and gives restriction ~2 %; not used for float32
-  // interpolation, which it slows down.
+  // GB per 20,000 faces) and gives restriction ~2 %.  Float32 interpolation,
+  // which it slows down, takes runs of four blocks per XCD instead (mode 2).
   int xcd_remap = 1;
   // Calls with at most this many unknowns per cell run the small-U body
   // (lanes over stencil points and rows instead of unknowns; every float32

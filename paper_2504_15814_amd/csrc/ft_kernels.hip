@@ -16,7 +16,7 @@ struct Geometry {
   int64_t n_faces;
   int anchors;  // expansion anchors per face, E * E
   int waves_per_block;
-  int xcd_remap;  // 1: consecutive logical blocks land on one XCD
+  int xcd_remap;  // block numbering, see logical_block (0, 1 or 2)
   int layout;     // kFaceBuffers or kPatches
 };
 
@@ -210,8 +210,9 @@ hipError_t launch_apply(const ft_operator* op, const LaunchArgs& la, const Launc
   g.waves_per_block = cfg.waves_per_block;
   // XCD-contiguous numbering: restriction 2.5 % faster, float64
   // interpolation unchanged (half the L2 misses), float32 interpolation 3-5 %
-  // slower.
-  g.xcd_remap = (op->direction == FT_INTERPOLATE && la.dtype != FT_F64) ? 0 : cfg.xcd_remap;
+  // slower; there runs of four blocks per XCD (mode 2) cut the HBM reads from
+  // 2.3x to 1.4x of the algorithmic bytes at the same speed.
+  g.xcd_remap = (op->direction == FT_INTERPOLATE && la.dtype != FT_F64) ? 2 : cfg.xcd_remap;
   g.layout = la.layout;
   const bool small = la.U <= cfg.small_unknowns[op->direction];
   if (small) g.xcd_remap = cfg.xcd_remap;
