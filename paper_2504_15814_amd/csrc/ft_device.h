@@ -185,7 +185,7 @@ __device__ __forceinline__ int row_cell(const ItemGeom& g, const int r, const in
 // three cells along b back to back (b is axis 0, adjacent in memory, when
 // the normal is axis 1 or 2); with X = 1, for faces whose normal is axis 0,
 // the k layers of one column back to back.  Against row order, float64
-// interpolation 3-7 % and float32 4-10 % faster (same-box A/B); one order per
+// interpolation 3-7 % and float32 4-10 % faster (same-machine A/B); one order per
 // normal axis, three store sequences, was slower than these two.
 template <int R, int X>
 __device__ __forceinline__ constexpr int store_row(const int i) {

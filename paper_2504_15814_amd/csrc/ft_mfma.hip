@@ -13,7 +13,7 @@ namespace ft {
 
 // Six waves per SIMD: the accumulators then live in 80 VGPRs (the compiler's
 // own choice, 58 VGPRs + 32 AGPRs, allows five; six-term Taylor-3
-// interpolation 2-3 % faster, same-box A/B).  The six-term form spills three
+// interpolation 2-3 % faster, same-machine A/B).  The six-term form spills three
 // registers under this hint; five waves per SIMD avoids that and is no faster.
 template <int R, int EC, int TERMS, int DIM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void interp_mfma_kernel(
