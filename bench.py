@@ -92,18 +92,30 @@ def algorithmic_bytes(op, orientation, subface, U, elem_bytes):
 KERNEL_SOURCES = ("ft_device.h", "ft_kernels.hip", "ft_mfma.hip", "ft_kernels.h")
 
 
+def kernel_source_hash():
+    """sha256 prefix of the kernel sources with comments and blank space
+    removed (a comment edit does not invalidate recorded counters)."""
+    import hashlib
+    import re
+
+    csrc = os.path.join(ROOT, "paper_2504_15814_amd", "csrc")
+    code = []
+    for f in KERNEL_SOURCES:
+        text = open(os.path.join(csrc, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code.append("\n".join(line.strip() for line in text.splitlines() if line.strip()))
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
+
+
 def recorded_traffic(kernel_name, mode="f64"):
     """HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) recorded for this kernel
     in profiles/, or None if the kernel sources changed since they were taken."""
-    import hashlib
-
     prof = os.path.join(ROOT, "profiles", "transfer_kernels_workload2.md")
-    csrc = os.path.join(ROOT, "paper_2504_15814_amd", "csrc")
     try:
         text = open(prof).read()
         rec = json.loads(text.split("```json")[1].split("```")[0])
-        cur = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                      for f in KERNEL_SOURCES)).hexdigest()[:16]
+        cur = kernel_source_hash()
         if rec.get("kernel_source_sha256_16") != cur:
             return None
         k = rec["kernels"][f"{mode}/{kernel_name}"]
