@@ -129,3 +129,38 @@ def test_graph_survives_schedule_change_and_plan_destruction(dev):
         torch.cuda.synchronize()
         assert torch.equal(c, c_ref) and torch.equal(f, f_ref)
     graph.destroy()
+
+
+def test_graph_of_several_plans_outlives_them(dev):
+    """transfer_plans_capture: the mix's restriction batches and its
+    interpolation batches as two plans in one graph equal the single plan
+    over all batches bit for bit (the faces are independent), also after
+    both plans are destroyed; bad arguments are refused."""
+    mb, ops, batches = _mix(dev)
+    c_ref, f_ref = mb.coarse.clone(), mb.fine.clone()
+    api.build_transfer_plan(batches, mb.U, c_ref, f_ref, mode=api.FT_F32_BF16X6).run()
+    torch.cuda.synchronize()
+    c, f = mb.coarse.clone(), mb.fine.clone()
+    plans = [api.build_transfer_plan([b for b in batches if b[0].direction == d], mb.U, c, f,
+                                     mode=api.FT_F32_BF16X6) for d in (1, 0)]
+    graph = api.transfer_plans_capture(plans, steps=1)
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 2)(plans[0].handle, None)
+    assert lib.transfer_plans_capture(arr, 2, 1, ctypes.byref(h)) == api.FT_ERR_INVALID
+    arr = (ctypes.c_void_p * 2)(plans[0].handle, plans[1].handle)
+    assert lib.transfer_plans_capture(arr, 0, 1, ctypes.byref(h)) == api.FT_ERR_INVALID
+    assert lib.transfer_plans_capture(arr, 2, 0, ctypes.byref(h)) == api.FT_ERR_INVALID
+    assert h.value is None
+    for p in plans:
+        p.destroy()
+    for _ in range(3):
+        c.copy_(mb.coarse)
+        f.copy_(mb.fine)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(c, c_ref) and torch.equal(f, f_ref)
+    graph.destroy()
+    for op in ops.values():
+        assert op.errors() == 0
