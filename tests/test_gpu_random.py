@@ -2,7 +2,8 @@
 scheme, direction, unknown count, face count and the (orientation, subface)
 mix drawn from a fixed generator, so that combinations no hand-written case
 names are covered too.  FP64 at 1e-12 relative; float32 storage on the
-vector ALUs at 1e-5."""
+vector ALUs at 1e-5; float64 fine data restricted into float32 coarse faces
+within one float32 rounding."""
 
 import numpy as np
 import pytest
@@ -56,6 +57,34 @@ def test_random_configuration_f32(dev, case):
     assert np.array_equal(got[copy], want[copy])
     emax, _ = gh.rel_errors(got, want, mask, U)
     assert emax.max() < 1e-5
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c[6] == 1],
+                         ids=[f"c{c[0]}" for c in CASES if c[6] == 1])
+def test_random_restriction_f64_to_f32(dev, case):
+    """FT_F64_TO_F32 restriction of the float64 data: bitwise the FP64
+    result rounded to float32, within 2^-24 |y| + 2e-12 max|y| of the oracle,
+    injected values exact, untouched cells kept."""
+    i, scheme, p, k, U, n_faces, _ = case
+    batch = wl.uniform_faces(n_faces, p, k, U, seed=9000 + i, device=dev)
+    op = api.build_transfer_operator(api.FT_RESTRICT, scheme, p, k)
+    d = (batch.orientation, batch.subface, batch.coarse_offset, batch.fine_offset)
+    got = torch.full(batch.coarse.shape, gh.SENTINEL, dtype=torch.float32, device=dev)
+    ref = torch.full_like(batch.coarse, gh.SENTINEL)
+    api.restrict_faces(op, *d, U, batch.fine, got, mode=api.FT_F64_TO_F32)
+    api.restrict_faces(op, *d, U, batch.fine, ref)
+    torch.cuda.synchronize()
+    assert op.errors() == 0
+    before = np.full(got.numel(), np.float32(gh.SENTINEL), dtype=np.float64)
+    want, (o, s, co) = gh.run_oracle(1, scheme, batch, batch.fine.cpu().numpy(), before)
+    mask, copy = gh.written_mask(1, scheme, p, k, U, o, s, co, len(want))
+    g = got.double().cpu().numpy()
+    assert np.array_equal(g[~mask], before[~mask])
+    assert np.array_equal(g, ref.cpu().numpy().astype(np.float32).astype(np.float64))
+    w = want[mask].reshape(-1, U)
+    bound = 2.0**-24 * np.abs(w) + 2e-12 * np.abs(w).max(axis=0)
+    assert (np.abs(g[mask].reshape(-1, U) - w) <= bound).all()
+    assert np.array_equal(g[copy], want[copy].astype(np.float32).astype(np.float64))
 
 
 def _patch_cases(n, seed=1581):
