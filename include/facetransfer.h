@@ -121,7 +121,8 @@ extern "C" {
  * FT_F64_TO_F32: restriction only, face buffers only: float64 fine data,
  *                float64 sums, float32 coarse faces (each output is the
  *                FT_F64 result rounded once to float32).  Restriction's
- *                extrapolation rows (weights of 1-norm up to about 400)
+ *                extrapolation rows (Section 3: coarse layers without a
+ *                coinciding fine cell; weights of 1-norm up to about 400)
  *                amplify the rounding of float32-stored fine data to about
  *                1e-5 of the field; with float64 fine data the coarse faces
  *                carry only their own float32 rounding, and interpolation
