@@ -391,6 +391,10 @@ def _plan_batches(batches):
 
 
 def build_transfer_plan(batches, unknowns, coarse, fine, mode=None, flags=0):
+    """A plan over batches of (operator, orientation, subface,
+    coarse_offset, fine_offset); `coarse` and `fine` are the pools every
+    batch addresses (mode FT_F64_TO_F32: restriction batches only, float64
+    fine and float32 coarse pools)."""
     dt = _mode(coarse, fine, mode)
     arr, keep = _plan_batches(batches)
     keep.extend([coarse, fine])
